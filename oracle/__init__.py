@@ -1,0 +1,238 @@
+"""Float64 CPU oracle for synchronous PCDM1 on the LASSO (test infrastructure).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It is a plain serial implementation written from the
+paper (Richtarik & Takac, "Parallel Coordinate Descent Methods for Big Data
+Optimization"); the numbered facts each function follows are cited in
+``pcdm_oracle.c``.  It shares no code with the HIP library.
+
+Functions whose result has no independent pin say "parity unpinned" in their
+docstring (none at present: every public function is pinned by a test under
+``tests/test_oracle_*.py``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pcdm_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_handle = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_I64P = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_F64P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_f64 = ctypes.c_double
+
+
+def _lib():
+    global _handle
+    with _lock:
+        if _handle is None:
+            lib = ctypes.CDLL(build())
+            sig = {
+                "orc_beta_nice": (_f64, [_i64, _i64, _i64]),
+                "orc_beta_uniform": (_f64, [_i64, _i64]),
+                "orc_beta_binomial": (_f64, [_i64, _i64, _i64, _f64]),
+                "orc_omega": (_i64, [_i64, _i64, _I64P, _I32P, _F64P]),
+                "orc_lipschitz": (None, [_i64, _I64P, _F64P, _F64P]),
+                "orc_splitmix64": (_u64, [_u64, _u64]),
+                "orc_fmix32": (ctypes.c_uint32, [ctypes.c_uint32]),
+                "orc_sample_nice": (ctypes.c_int, [_u64, _u64, _i64, _i64, _I64P]),
+                "orc_soft": (_f64, [_f64, _f64]),
+                "orc_residual": (None, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _F64P, _F64P]),
+                "orc_objective": (_f64, [_i64, _i64, _F64P, _F64P, _f64]),
+                "orc_gradient": (None, [_i64, _I64P, _I32P, _F64P, _F64P, _F64P]),
+                "orc_dual_gap": (_f64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _F64P, _F64P, _f64,
+                                        ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
+                "orc_step_with_set": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64,
+                                             _i64, _I64P, _F64P, _F64P]),
+                "orc_pcdm_run": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64,
+                                        _i64, _u64, _i64, _i64, _F64P, _F64P]),
+            }
+            for name, (res, args) in sig.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _handle = lib
+    return _handle
+
+
+# --------------------------------------------------------------------------- #
+# scalar rules
+# --------------------------------------------------------------------------- #
+
+def beta_nice(omega: int, tau: int, n: int) -> float:
+    """beta for the tau-nice sampling (Table ESO; theorem ESO for nice samplings)."""
+    return _lib().orc_beta_nice(int(omega), int(tau), int(n))
+
+
+def beta_uniform(omega: int, tau: int) -> float:
+    """Conservative beta = min(omega, tau) of any tau-uniform sampling (Table ESO)."""
+    return _lib().orc_beta_uniform(int(omega), int(tau))
+
+
+def beta_binomial(omega: int, tau: int, n: int, pb: float) -> float:
+    """beta of the (tau, p_b)-binomial sampling (Table ESO)."""
+    return _lib().orc_beta_binomial(int(omega), int(tau), int(n), float(pb))
+
+
+def soft(u: float, c: float) -> float:
+    """Soft threshold sign(u)*max(|u|-c, 0): the l1 block minimiser."""
+    return _lib().orc_soft(float(u), float(c))
+
+
+def splitmix64(state: int, t: int) -> int:
+    """Output number t of SplitMix64 started at ``state``."""
+    return int(_lib().orc_splitmix64(state & (2**64 - 1), t & (2**64 - 1)))
+
+
+def fmix32(h: int) -> int:
+    """MurmurHash3 32-bit finaliser."""
+    return int(_lib().orc_fmix32(h & 0xFFFFFFFF))
+
+
+def sample_nice(seed: int, k: int, tau: int, n: int) -> np.ndarray:
+    """S_k of the tau-nice sampler, in slot order (int64 [tau])."""
+    out = np.empty(max(int(tau), 1), dtype=np.int64)
+    if _lib().orc_sample_nice(seed & (2**64 - 1), int(k), int(tau), int(n), out) != 0:
+        raise ValueError("bad sampler arguments")
+    return out[: int(tau)]
+
+
+# --------------------------------------------------------------------------- #
+# matrix helpers (float64 upcast of the stored values)
+# --------------------------------------------------------------------------- #
+
+def _arrays(A):
+    return (np.ascontiguousarray(A.col_ptr, dtype=np.int64),
+            np.ascontiguousarray(A.row_idx, dtype=np.int32),
+            np.ascontiguousarray(A.values_f64(), dtype=np.float64))
+
+
+def omega(A) -> int:
+    """Maximum number of nonzeros in a row of A."""
+    cp, ri, v = _arrays(A)
+    return int(_lib().orc_omega(A.m, A.n, cp, ri, v))
+
+
+def lipschitz(A) -> np.ndarray:
+    """L_i = ||a_i||^2 from the stored values."""
+    cp, _, v = _arrays(A)
+    L = np.empty(A.n)
+    _lib().orc_lipschitz(A.n, cp, v, L)
+    return L
+
+
+def residual(A, x, b) -> np.ndarray:
+    cp, ri, v = _arrays(A)
+    r = np.empty(A.m)
+    _lib().orc_residual(A.m, A.n, cp, ri, v, np.ascontiguousarray(x, np.float64),
+                        np.ascontiguousarray(b, np.float64), r)
+    return r
+
+
+def objective(A, x, b, lam) -> float:
+    r = residual(A, x, b)
+    return _lib().orc_objective(A.m, A.n, r, np.ascontiguousarray(x, np.float64), float(lam))
+
+
+def gradient(A, r) -> np.ndarray:
+    cp, ri, v = _arrays(A)
+    g = np.empty(A.n)
+    _lib().orc_gradient(A.n, cp, ri, v, np.ascontiguousarray(r, np.float64), g)
+    return g
+
+
+def dual_gap(A, b, x, lam, r=None):
+    """(gap, F, D) with theta = r*min(1, lam/||A^T r||_inf)."""
+    cp, ri, v = _arrays(A)
+    if r is None:
+        r = residual(A, x, b)
+    F, D = _f64(), _f64()
+    gap = _lib().orc_dual_gap(A.m, A.n, cp, ri, v, np.ascontiguousarray(b, np.float64),
+                              np.ascontiguousarray(x, np.float64), np.ascontiguousarray(r, np.float64),
+                              float(lam), ctypes.byref(F), ctypes.byref(D))
+    return gap, F.value, D.value
+
+
+class Solver:
+    """Serial float64 PCDM1 state: x, r = A x - b, step counter k.
+
+    ``beta_rule``: 'nice' (tau-nice beta) or 'uniform' (min(omega, tau)).
+    """
+
+    def __init__(self, A, b, lam, tau, seed=0, beta_rule="nice", beta=None, x0=None):
+        self.A = A
+        self.m, self.n = A.m, A.n
+        self.cp, self.ri, self.v = _arrays(A)
+        self.b = np.ascontiguousarray(b, np.float64)
+        self.lam = float(lam)
+        self.tau = int(tau)
+        self.seed = int(seed)
+        self.L = np.empty(self.n)
+        _lib().orc_lipschitz(self.n, self.cp, self.v, self.L)
+        self.omega = int(_lib().orc_omega(self.m, self.n, self.cp, self.ri, self.v))
+        if beta is not None:
+            self.beta = float(beta)
+        elif beta_rule == "nice":
+            self.beta = beta_nice(self.omega, self.tau, self.n)
+        elif beta_rule == "uniform":
+            self.beta = beta_uniform(self.omega, self.tau)
+        else:
+            raise ValueError(beta_rule)
+        self.x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64)
+        self.r = np.empty(self.m)
+        self.refresh()
+        self.k = 0
+        self.changed = 0
+
+    def refresh(self):
+        _lib().orc_residual(self.m, self.n, self.cp, self.ri, self.v, self.x, self.b, self.r)
+
+    def step(self, nsteps: int = 1) -> int:
+        c = _lib().orc_pcdm_run(self.m, self.n, self.cp, self.ri, self.v, self.L, self.lam,
+                                self.beta, self.tau, self.seed & (2**64 - 1), self.k, int(nsteps),
+                                self.x, self.r)
+        if c < 0:
+            raise RuntimeError("oracle step failed")
+        self.k += int(nsteps)
+        self.changed += int(c)
+        return int(c)
+
+    def step_with_set(self, S) -> int:
+        S = np.ascontiguousarray(S, dtype=np.int64)
+        c = _lib().orc_step_with_set(self.m, self.n, self.cp, self.ri, self.v, self.L, self.lam,
+                                     self.beta, S.size, S, self.x, self.r)
+        if c < 0:
+            raise ValueError("bad set")
+        return int(c)
+
+    def objective(self, fresh: bool = True) -> float:
+        r = residual(self.A, self.x, self.b) if fresh else self.r
+        return _lib().orc_objective(self.m, self.n, np.ascontiguousarray(r), self.x, self.lam)
+
+    def gap(self):
+        return dual_gap(self.A, self.b, self.x, self.lam, r=residual(self.A, self.x, self.b))
+
+    def steps_per_epoch(self) -> int:
+        return -(-self.n // self.tau)

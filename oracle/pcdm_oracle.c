@@ -1,0 +1,358 @@
+/*
+ * pcdm_oracle.c -- plain, serial, float64 reference of synchronous PCDM1 on the
+ * LASSO objective  F(x) = 0.5*||A x - b||^2 + lambda*||x||_1 .
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file's library.  It shares no
+ * code, header, table or constant generator with the HIP library; the
+ * sampler below is written from the published definitions of its parts.
+ *
+ * What each function follows (Richtarik & Takac, "Parallel Coordinate Descent
+ * Methods for Big Data Optimization"):
+ *   - beta for the tau-nice sampling: Table "ESO" (tau-nice row) and the
+ *     theorem "ESO for nice samplings"; beta = 1 + (omega-1)(tau-1)/max(1,n-1).
+ *   - beta for tau-uniform samplings: Table "ESO" (tau-uniform row) and the
+ *     theorem on proper uniform samplings; beta = min(omega, tau).
+ *   - omega = max number of nonzeros in a row of A (introduction, examples of
+ *     partially separable functions; contributions, item "partial separability").
+ *   - L_i = ||a_i||_2^2, w = L (contributions, "partial separability"; the
+ *     LASSO experiment uses w = L).
+ *   - the step: Algorithm PCDM1 with the update h(x) = argmin H_{beta,w}(x,.)
+ *     (eqs. h(x) and H_{beta,w}); for Omega = lambda*|.| and blocks of size 1
+ *     the block minimiser is a soft threshold (derivation in the function).
+ *   - every i in S_k is updated from the same x_k (Step 4 "in parallel").
+ *   - the dual bound for the duality gap is standard LASSO duality.
+ *
+ * Numerics: float64, round to nearest, sums in ascending index order, no
+ * blocking or reordering beyond what is stated.  Scatter order inside a step:
+ * ascending coordinate index.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Step damping (Table ESO).                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* tau-nice sampling: beta = 1 + (omega-1)(tau-1)/max(1, n-1), w = L. */
+double orc_beta_nice(int64_t omega, int64_t tau, int64_t n)
+{
+    double den = (n - 1 > 1) ? (double)(n - 1) : 1.0;
+    return 1.0 + ((double)(omega - 1) * (double)(tau - 1)) / den;
+}
+
+/* any tau-uniform sampling: beta = min(omega, tau), w = L (monotone ESO). */
+double orc_beta_uniform(int64_t omega, int64_t tau)
+{
+    return (double)(omega < tau ? omega : tau);
+}
+
+/* (tau, p_b)-binomial sampling: beta = 1 + p_b(omega-1)(tau-1)/max(1, n-1). */
+double orc_beta_binomial(int64_t omega, int64_t tau, int64_t n, double pb)
+{
+    double den = (n - 1 > 1) ? (double)(n - 1) : 1.0;
+    return 1.0 + pb * ((double)(omega - 1) * (double)(tau - 1)) / den;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Structure of f.                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* omega = max_j #{i : A_ji != 0}: the degree of partial separability of
+ * 0.5*||Ax-b||^2 (each row term depends on the coordinates it touches). */
+int64_t orc_omega(int64_t m, int64_t n, const int64_t *col_ptr,
+                  const int32_t *row_idx, const double *val)
+{
+    int64_t *cnt = (int64_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    int64_t best = 0;
+    if (!cnt)
+        return -1;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            if (val[p] != 0.0)
+                cnt[row_idx[p]] += 1;
+    for (int64_t j = 0; j < m; ++j)
+        if (cnt[j] > best)
+            best = cnt[j];
+    free(cnt);
+    return best;
+}
+
+/* Block Lipschitz constants of grad f: L_i = ||a_i||^2. */
+void orc_lipschitz(int64_t n, const int64_t *col_ptr, const double *val, double *L)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            s += val[p] * val[p];
+        L[i] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* tau-nice sampler.                                                         */
+/*                                                                           */
+/* The paper fixes only the law: every subset of size tau is equally likely. */
+/* Concrete generator (written independently on the GPU side):              */
+/*   * SplitMix64 (Steele, Lea & Flood, 2014): output number t of the stream */
+/*     started at state s is mix64(s + (t+1)*0x9E3779B97F4A7C15) with        */
+/*     mix64(z): z=(z^(z>>30))*0xBF58476D1CE4E5B9; z=(z^(z>>27))*            */
+/*     0x94D049BB133111EB; return z^(z>>31).                                  */
+/*   * MurmurHash3's 32-bit finaliser fmix32 (Appleby) as Feistel round     */
+/*     function.                                                             */
+/*   * Step k's round keys: K_rho = low 32 bits of SplitMix64 output number  */
+/*     10k+rho of the stream started at seed XOR 0x5043444D4E494345,         */
+/*     rho = 0..9.                                                           */
+/*   * E_k: balanced 10-round Feistel network on [0, 4^h), h >= 1 minimal    */
+/*     with 4^h >= n; x -> (L,R) = (x >> h, x & (2^h-1)); each round         */
+/*     (L,R) <- (R, L ^ (fmix32(R ^ K_rho) & (2^h-1))); result (L<<h)|R.    */
+/*   * pi_k(j): cycle walking (Black & Rogaway, 2002): y = E_k(j), repeat    */
+/*     y = E_k(y) while y >= n.  pi_k is a permutation of [0, n).            */
+/*   * S_k = { pi_k(j) : 0 <= j < tau } (slot j holds pi_k(j)).              */
+/*   Ten rounds, not four: on the tiny domains of small n (4^h = 16 for      */
+/*   n = 6) four rounds give a subset law measurably far from uniform.       */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_splitmix64(uint64_t state, uint64_t t)
+{
+    return orc_mix64(state + (t + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+uint32_t orc_fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6BU;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35U;
+    h ^= h >> 16;
+    return h;
+}
+
+static int orc_half_bits(int64_t n)
+{
+    int h = 1;
+    while ((((uint64_t)1) << (2 * h)) < (uint64_t)n)
+        ++h;
+    return h;
+}
+
+static uint64_t orc_feistel(uint64_t x, int h, const uint32_t key[10])
+{
+    uint32_t mask = (uint32_t)((((uint64_t)1) << h) - 1);
+    uint32_t left = (uint32_t)(x >> h), right = (uint32_t)(x & mask);
+    for (int rho = 0; rho < 10; ++rho) {
+        uint32_t t = left ^ (orc_fmix32(right ^ key[rho]) & mask);
+        left = right;
+        right = t;
+    }
+    return ((uint64_t)left << h) | right;
+}
+
+/* Writes S_k into out[0..tau).  Returns 0, or -1 for bad arguments. */
+int orc_sample_nice(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int64_t *out)
+{
+    uint32_t key[10];
+    int h;
+    if (n < 1 || n > 2147483647LL || tau < 0 || tau > n)
+        return -1;
+    for (int rho = 0; rho < 10; ++rho)
+        key[rho] = (uint32_t)orc_splitmix64(seed ^ 0x5043444D4E494345ULL, 10 * k + (uint64_t)rho);
+    h = orc_half_bits(n);
+    for (int64_t j = 0; j < tau; ++j) {
+        uint64_t y = orc_feistel((uint64_t)j, h, key);
+        while (y >= (uint64_t)n)
+            y = orc_feistel(y, h, key);
+        out[j] = (int64_t)y;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Objective pieces.                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* soft(u, c) = sign(u) * max(|u| - c, 0); soft(+-c, c) = 0. */
+double orc_soft(double u, double c)
+{
+    if (u > c)
+        return u - c;
+    if (u < -c)
+        return u + c;
+    return 0.0;
+}
+
+/* r = A x - b. */
+void orc_residual(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                  const double *val, const double *x, const double *b, double *r)
+{
+    for (int64_t j = 0; j < m; ++j)
+        r[j] = -b[j];
+    for (int64_t i = 0; i < n; ++i) {
+        if (x[i] == 0.0)
+            continue;
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            r[row_idx[p]] += val[p] * x[i];
+    }
+}
+
+/* F(x) = 0.5*||r||^2 + lambda*||x||_1 with r = A x - b given. */
+double orc_objective(int64_t m, int64_t n, const double *r, const double *x, double lambda)
+{
+    double s = 0.0, t = 0.0;
+    for (int64_t j = 0; j < m; ++j)
+        s += r[j] * r[j];
+    for (int64_t i = 0; i < n; ++i)
+        t += fabs(x[i]);
+    return 0.5 * s + lambda * t;
+}
+
+/* g_i = grad_i f(x) = a_i^T r for all i. */
+void orc_gradient(int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                  const double *val, const double *r, double *g)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            s += val[p] * r[row_idx[p]];
+        g[i] = s;
+    }
+}
+
+/* LASSO dual: D(theta) = -0.5*||theta||^2 - b^T theta on ||A^T theta||_inf <= lambda.
+ * theta = s*r with s = min(1, lambda/||A^T r||_inf) is dual feasible; returns
+ * the gap F(x) - D(theta) >= 0 (weak duality) and writes F and D. */
+double orc_dual_gap(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                    const double *val, const double *b, const double *x, const double *r,
+                    double lambda, double *F_out, double *D_out)
+{
+    double gmax = 0.0, rr = 0.0, br = 0.0, s, F, D;
+    for (int64_t i = 0; i < n; ++i) {
+        double g = 0.0;
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            g += val[p] * r[row_idx[p]];
+        if (fabs(g) > gmax)
+            gmax = fabs(g);
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        rr += r[j] * r[j];
+        br += b[j] * r[j];
+    }
+    s = (gmax > lambda) ? lambda / gmax : 1.0;
+    F = orc_objective(m, n, r, x, lambda);
+    D = -0.5 * s * s * rr - s * br;
+    if (F_out)
+        *F_out = F;
+    if (D_out)
+        *D_out = D;
+    return F - D;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PCDM1 step.                                                               */
+/* ------------------------------------------------------------------------ */
+
+static int orc_cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * One synchronous step x <- x + (h(x))_[S] on the given set S (size tau), with
+ * r = A x - b maintained.
+ *
+ * h(x)^(i) minimises  g_i t + (beta L_i / 2) t^2 + lambda |x_i + t|  over t
+ * (the block form of H_{beta,w} with w = L, N_i = 1).  With u = x_i - g_i/(beta L_i)
+ * the minimiser of (beta L_i/2)(x_i + t - u)^2 + lambda|x_i + t| is
+ * x_i + t = soft(u, lambda/(beta L_i)).
+ *
+ * All g_i use the same r (= A x_k - b).  Afterwards x and r are updated in
+ * ascending coordinate order.  Returns -1 if S holds a duplicate or an index
+ * out of range, else the number of coordinates whose value changed.
+ */
+int64_t orc_step_with_set(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                          const double *val, const double *L, double lambda, double beta,
+                          int64_t tau, const int64_t *S, double *x, double *r)
+{
+    int64_t *ids = (int64_t *)malloc((size_t)(tau > 0 ? tau : 1) * sizeof(int64_t));
+    double *delta = (double *)malloc((size_t)(tau > 0 ? tau : 1) * sizeof(double));
+    int64_t changed = 0;
+    (void)m;
+    if (!ids || !delta) {
+        free(ids);
+        free(delta);
+        return -1;
+    }
+    memcpy(ids, S, (size_t)tau * sizeof(int64_t));
+    qsort(ids, (size_t)tau, sizeof(int64_t), orc_cmp_i64);
+    for (int64_t t = 0; t < tau; ++t) {
+        if (ids[t] < 0 || ids[t] >= n || (t > 0 && ids[t] == ids[t - 1])) {
+            free(ids);
+            free(delta);
+            return -1;
+        }
+    }
+    /* phase 1: every update from the same residual */
+    for (int64_t t = 0; t < tau; ++t) {
+        int64_t i = ids[t];
+        double g = 0.0, u, xn;
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            g += val[p] * r[row_idx[p]];
+        u = x[i] - g / (beta * L[i]);
+        xn = orc_soft(u, lambda / (beta * L[i]));
+        delta[t] = xn - x[i];
+    }
+    /* phase 2: apply */
+    for (int64_t t = 0; t < tau; ++t) {
+        int64_t i = ids[t];
+        if (delta[t] == 0.0)
+            continue;
+        ++changed;
+        x[i] += delta[t];
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            r[row_idx[p]] += delta[t] * val[p];
+    }
+    free(ids);
+    free(delta);
+    return changed;
+}
+
+/*
+ * nsteps steps of PCDM1 with the tau-nice sampler, steps k0 .. k0+nsteps-1.
+ * x and r (= A x - b on entry) are updated in place.  Returns the total count
+ * of coordinates that changed, or -1 on error.
+ */
+int64_t orc_pcdm_run(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                     const double *val, const double *L, double lambda, double beta,
+                     int64_t tau, uint64_t seed, int64_t k0, int64_t nsteps,
+                     double *x, double *r)
+{
+    int64_t *S = (int64_t *)malloc((size_t)(tau > 0 ? tau : 1) * sizeof(int64_t));
+    int64_t total = 0;
+    if (!S)
+        return -1;
+    for (int64_t k = k0; k < k0 + nsteps; ++k) {
+        int64_t c;
+        if (orc_sample_nice(seed, (uint64_t)k, tau, n, S) != 0) {
+            free(S);
+            return -1;
+        }
+        c = orc_step_with_set(m, n, col_ptr, row_idx, val, L, lambda, beta, tau, S, x, r);
+        if (c < 0) {
+            free(S);
+            return -1;
+        }
+        total += c;
+    }
+    free(S);
+    return total;
+}
