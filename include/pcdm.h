@@ -1,0 +1,197 @@
+/*
+ * pcdm.h -- C ABI of the MI355X (gfx950) library for synchronous parallel
+ * coordinate descent (PCDM1) on the LASSO
+ *
+ *     minimise  F(x) = 0.5 * ||A x - b||_2^2 + lambda * ||x||_1 ,  x in R^n,
+ *
+ * the composite problem of the paper's problem statement (eq. P) with the
+ * partially separable smooth part f(x) = 0.5||Ax-b||^2 and the separable
+ * regulariser Omega(x) = lambda||x||_1 (Richtarik & Takac, "Parallel
+ * Coordinate Descent Methods for Big Data Optimization"; the LASSO of the
+ * experiments section, with lambda general).
+ *
+ * One step (Algorithm PCDM1):
+ *   1. draw S_k, a tau-nice random set of tau distinct coordinates
+ *      (section "Block Samplings", nice sampling);
+ *   2. for every i in S_k, from the same residual r = A x_k - b:
+ *        g_i = a_i^T r                              (partial derivative),
+ *        u   = x_i - g_i / (beta L_i),
+ *        x_i <- sign(u) max(|u| - lambda/(beta L_i), 0)
+ *      i.e. x_i + h^(i)(x_k) with h(x) = argmin H_{beta,w}(x, .) and w = L,
+ *      L_i = ||a_i||^2, beta = 1 + (omega-1)(tau-1)/max(1, n-1)
+ *      (Table "ESO", tau-nice row; theorem "ESO for nice samplings");
+ *   3. r <- r + sum_{i in S_k} delta_i a_i (residual kept by scatter-add).
+ * omega is the largest number of nonzeros in a row of A (degree of partial
+ * separability).
+ *
+ * Every function returns an int status: PCDM_OK (0) or a negative
+ * pcdm_status; pcdm_last_error() then gives a message (thread-local, valid
+ * until the next call on the same thread).  No C++ exception and no exit()
+ * crosses this boundary.  A handle is not thread-safe: calls on one handle
+ * must be serialised by the caller; handles are independent of each other.
+ *
+ * Device work is enqueued on the HIP stream passed in (void* = hipStream_t,
+ * NULL = the default stream) and is asynchronous unless stated otherwise.
+ */
+#ifndef PCDM_H
+#define PCDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCDM_OK = 0,
+    PCDM_EINVAL = -1,   /* invalid argument or invalid matrix            */
+    PCDM_ENOMEM = -2,   /* device allocation failed                      */
+    PCDM_EDEVICE = -3,  /* HIP runtime error (no device, launch failure) */
+    PCDM_ESTATE = -4,   /* call not valid for this handle's state        */
+    PCDM_ENOTCONV = -5  /* iterative solve did not reach its tolerance   */
+} pcdm_status;
+
+/* Value types.  The dtype of A's values selects the arithmetic:
+ *   PCDM_F64  : values, x and r in float64, float64 sums;
+ *   PCDM_F32  : values, x and r in float32, float32 dot products;
+ *   PCDM_BF16 : values stored as bfloat16 (raw uint16 bit patterns), x and r
+ *               in float32, float32 dot products.
+ * In every mode the periodic residual refresh r = A x - b, the objective and
+ * the duality gap are computed in float64. */
+typedef enum { PCDM_F32 = 0, PCDM_BF16 = 1, PCDM_F64 = 2 } pcdm_dtype;
+
+/* Compressed sparse column matrix; column i holds coordinate i's data a_i
+ * (the paper stores A by columns: coordinate i needs only a_i).
+ *   col_ptr [n+1] int64 : col_ptr[0] = 0, non-decreasing, col_ptr[n] = nnz;
+ *   row_idx [nnz] int32 : rows of column i at col_ptr[i] .. col_ptr[i+1]-1,
+ *                         each in [0, m), unique within the column (any order);
+ *   values  [nnz]       : of type dtype, finite.
+ * on_device = 1: col_ptr, row_idx, values (and the b passed with them) are
+ * device pointers (e.g. torch tensors on the GPU); 0: host pointers.
+ * The library copies what it needs; the caller keeps ownership. */
+typedef struct pcdm_csc {
+    int64_t m, n, nnz;
+    const int64_t *col_ptr;
+    const int32_t *row_idx;
+    const void *values;
+    int32_t dtype;
+    int32_t on_device;
+} pcdm_csc;
+
+typedef struct pcdm_problem pcdm_problem; /* opaque, owned by the library */
+
+typedef struct pcdm_info {
+    int64_t m, n, nnz;
+    int64_t tau;
+    int64_t k;               /* steps taken so far (the sampler counter)          */
+    int64_t omega;           /* max nonzeros in a row (measured at create)        */
+    int64_t refresh_every;   /* steps between float64 residual refreshes; 0 = off */
+    int64_t nonzero_updates; /* coordinate updates with delta != 0 (since create  */
+                             /* or the last "reset_counters"); read synchronously */
+    int64_t stored_nnz;      /* entries in the device layout (columns padded)     */
+    double beta;             /* step damping in use                               */
+    double lambda;
+    double atb_inf;          /* ||A^T b||_inf in float64 from the stored A        */
+    int32_t dtype;
+    int32_t beta_rule;       /* 0 = tau-nice, 1 = tau-uniform min(omega,tau),     */
+                             /* 2 = explicit value set with option "beta"         */
+    int32_t lanes_per_column;/* step-kernel schedule in use                      */
+    int32_t reserved;
+} pcdm_info;
+
+/*
+ * Create a problem and copy A and b into library-owned device memory.
+ *   A       : matrix (validated; see pcdm_csc);
+ *   b       : [m] float64, host or device as A->on_device says;
+ *   lambda  : >= 0 and finite;
+ *   tau     : sampled coordinates per step, 1 <= tau <= n;
+ *   seed    : key of the tau-nice sampler (S_k depends on (seed, k) only).
+ * Requires 1 <= m <= 2^31 - 1 and 1 <= n <= 2^31 - 2.  Rejects (PCDM_EINVAL) empty or all-zero
+ * columns (the paper assumes L_i > 0), repeated rows in a column, rows out
+ * of range, non-finite values, a malformed col_ptr.  x starts at 0 and
+ * r = -b.  Runs on the default stream and returns after the device work is
+ * complete.  On failure *out is set to NULL.
+ */
+int pcdm_create(const pcdm_csc *A, const double *b, double lambda, int64_t tau,
+                uint64_t seed, pcdm_problem **out);
+
+/* Free all device memory of the handle (synchronises the device). NULL is a no-op. */
+int pcdm_destroy(pcdm_problem *h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *pcdm_last_error(void);
+
+/*
+ * Set a numeric option.  Keys:
+ *   "refresh_every"    steps between float64 refreshes r = A x - b (default
+ *                      ceil(n/tau), one epoch; 0 disables);
+ *   "beta_rule"        0 = tau-nice beta (default), 1 = min(omega, tau);
+ *   "beta"             explicit beta > 0 (sets beta_rule 2);
+ *   "lambda"           new lambda >= 0;
+ *   "tau"              new tau in [1, n] (beta recomputed by the rule);
+ *   "lanes_per_column" 0 = automatic, or 1, 2, 4, 8, 16, 32, 64 lanes
+ *                      cooperating on one sampled column;
+ *   "reset_counters"   any value: zero nonzero_updates.
+ * Unknown keys and out-of-range values give PCDM_EINVAL.
+ */
+int pcdm_set_option(pcdm_problem *h, const char *key, double value);
+
+/* Fill *out (synchronises the handle's last stream for nonzero_updates). */
+int pcdm_get_info(pcdm_problem *h, pcdm_info *out);
+
+/*
+ * Advance nsteps synchronous PCDM1 steps (k -> k + nsteps) on `stream`.
+ * Every refresh_every steps (counted by k) the residual is recomputed in
+ * float64 from x and rounded to the working type.  Asynchronous.
+ */
+int pcdm_step(pcdm_problem *h, int64_t nsteps, void *stream);
+
+/*
+ * F(x) = 0.5||A x - b||^2 + lambda||x||_1 with A x - b recomputed in float64
+ * (the working residual is not modified).  If dual_gap is not NULL, also the
+ * duality gap F(x) - D(theta) for theta = s r, s = min(1, lambda/||A^T r||_inf),
+ * D(theta) = -0.5||theta||^2 - b^T theta (one extra pass over A).  Both are
+ * >= 0 up to rounding and bound F(x) - F*.  Synchronous (waits on `stream`).
+ */
+int pcdm_objective(pcdm_problem *h, double *F, double *dual_gap, void *stream);
+
+/* Copy x (n values) to x_out, converted to dtype (PCDM_F32 or PCDM_F64),
+ * host or device memory.  Host copies are synchronous. */
+int pcdm_get_x(pcdm_problem *h, void *x_out, int32_t dtype, int32_t on_device, void *stream);
+
+/* Overwrite x from x (n values of dtype PCDM_F32 / PCDM_F64, host or device),
+ * set the step counter to k (resume), and recompute r = A x - b in float64. */
+int pcdm_set_x(pcdm_problem *h, const void *x, int32_t dtype, int32_t on_device,
+               int64_t k, void *stream);
+
+/* Copy the working residual r (m values, widened to float64) to r_out. */
+int pcdm_get_residual(pcdm_problem *h, double *r_out, int32_t on_device, void *stream);
+
+/*
+ * Reverse-mode derivative through the current iterate, taken as the LASSO
+ * solution: with S = {i : x_i != 0}, s = sign(x_S) and A_S^T A_S x_S =
+ * A_S^T b - lambda s on a stable support,
+ *     dL/db = A_S v,   dL/dlambda = -s^T v,   where A_S^T A_S v = (dL/dx)_S.
+ * v is found by PCDM steps (lambda = 0, same kernels) on
+ * q(v) = 0.5||A_S v||^2 - g^T v until ||A_S^T A_S v - g||_inf <= tol * ||g||_inf
+ * (option values at create: tol 1e-6, at most 20000 epochs).
+ *   dL_dx [n] float64, dL_db [m] float64 (out), dL_dlambda (out, host scalar);
+ * dL_dx and dL_db are host or device as on_device says.  Synchronous.
+ * PCDM_ENOTCONV if the tolerance is not met (outputs still written).
+ */
+int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db,
+                       double *dL_dlambda, int32_t on_device, void *stream);
+
+/*
+ * The tau-nice sampler on its own: writes S_k = {pi_k(j) : 0 <= j < tau}
+ * for key (seed, k) into out_device[0..tau) (int32, device memory), in slot
+ * order.  Same sets as pcdm_step draws.  Asynchronous.
+ */
+int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device,
+                void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCDM_H */

@@ -1,0 +1,172 @@
+"""Python face of the C ABI: same operations, argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts numpy
+arrays or torch tensors into pointers and sizes, passes torch's current HIP
+stream, and raises :class:`PCDMError` on a negative status.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from ._lib import (PCDM_BF16, PCDM_F32, PCDM_F64, PCDMError, check, load, pcdm_csc,  # noqa: F401
+                   pcdm_info)
+
+_NP_DTYPE = {np.dtype(np.float32): PCDM_F32, np.dtype(np.float64): PCDM_F64, np.dtype(np.uint16): PCDM_BF16}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream() -> Optional[int]:
+    """Raw hipStream_t of torch's current stream (None when no GPU)."""
+    try:
+        torch = _torch()
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+def _ptr(a) -> int:
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+class Problem:
+    """One LASSO problem held by the library (``pcdm_create`` .. ``pcdm_destroy``).
+
+    ``A`` is a CSC with host numpy arrays (``workloads.CSC``: float64, float32
+    or bf16 bits as uint16) or an object with attributes m, n, col_ptr,
+    row_idx, values holding CUDA torch tensors (float64, float32 or bfloat16);
+    ``b`` is float64 in the same place.
+    """
+
+    def __init__(self, A, b, lam: float, tau: int, seed: int = 0):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        on_dev = not isinstance(A.values, np.ndarray)
+        if on_dev:
+            torch = _torch()
+            tmap = {torch.float32: PCDM_F32, torch.float64: PCDM_F64, torch.bfloat16: PCDM_BF16}
+            vals = A.values.contiguous()
+            cp = A.col_ptr.to(torch.int64).contiguous()
+            ri = A.row_idx.to(torch.int32).contiguous()
+            bb = b.to(torch.float64).contiguous()
+            dtype = tmap[vals.dtype]
+            nnz = int(vals.numel())
+        else:
+            vals = np.ascontiguousarray(A.values)
+            cp = np.ascontiguousarray(A.col_ptr, dtype=np.int64)
+            ri = np.ascontiguousarray(A.row_idx, dtype=np.int32)
+            bb = np.ascontiguousarray(b, dtype=np.float64)
+            dtype = _NP_DTYPE[vals.dtype]
+            nnz = int(vals.size)
+        self._keep = (vals, cp, ri, bb)
+        desc = pcdm_csc(int(A.m), int(A.n), nnz, _ptr(cp), _ptr(ri), _ptr(vals), dtype, int(on_dev))
+        if on_dev:
+            _torch().cuda.current_stream().synchronize()
+        check(self._lib.pcdm_create(ctypes.byref(desc), _ptr(bb), float(lam), int(tau),
+                                    int(seed) & (2**64 - 1), ctypes.byref(self._h)))
+        self._keep = None
+        self.m, self.n, self.dtype = int(A.m), int(A.n), dtype
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            check(self._lib.pcdm_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- method ---------------------------------------------------------------
+    def step(self, nsteps: int = 1, stream: Optional[int] = None) -> None:
+        s = current_stream() if stream is None else stream
+        check(self._lib.pcdm_step(self._h, int(nsteps), s))
+
+    def objective(self, gap: bool = False, stream: Optional[int] = None):
+        """(F, gap or None), both computed in float64 on the device."""
+        s = current_stream() if stream is None else stream
+        F = ctypes.c_double()
+        G = ctypes.c_double()
+        check(self._lib.pcdm_objective(self._h, ctypes.byref(F), ctypes.byref(G) if gap else None, s))
+        return F.value, (G.value if gap else None)
+
+    def set_option(self, key: str, value: float) -> None:
+        check(self._lib.pcdm_set_option(self._h, key.encode(), float(value)))
+
+    def info(self) -> dict:
+        inf = pcdm_info()
+        check(self._lib.pcdm_get_info(self._h, ctypes.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in pcdm_info._fields_}
+        d["lambda"] = d.pop("lambda_")
+        return d
+
+    # -- state ------------------------------------------------------------------
+    def get_x(self, dtype=np.float64) -> np.ndarray:
+        out = np.empty(self.n, dtype=dtype)
+        code = PCDM_F64 if np.dtype(dtype) == np.float64 else PCDM_F32
+        check(self._lib.pcdm_get_x(self._h, out.ctypes.data, code, 0, current_stream()))
+        return out
+
+    def get_x_tensor(self, dtype=None):
+        torch = _torch()
+        dtype = dtype or torch.float64
+        out = torch.empty(self.n, dtype=dtype, device="cuda")
+        code = PCDM_F64 if dtype == torch.float64 else PCDM_F32
+        check(self._lib.pcdm_get_x(self._h, out.data_ptr(), code, 1, current_stream()))
+        return out
+
+    def set_x(self, x, k: int = 0) -> None:
+        if isinstance(x, np.ndarray):
+            xx = np.ascontiguousarray(x)
+            code = PCDM_F64 if xx.dtype == np.float64 else PCDM_F32
+            if xx.dtype not in (np.float64, np.float32):
+                xx = xx.astype(np.float64)
+                code = PCDM_F64
+            check(self._lib.pcdm_set_x(self._h, xx.ctypes.data, code, 0, int(k), current_stream()))
+        else:
+            torch = _torch()
+            xx = x.contiguous()
+            code = PCDM_F64 if xx.dtype == torch.float64 else PCDM_F32
+            check(self._lib.pcdm_set_x(self._h, xx.data_ptr(), code, 1, int(k), current_stream()))
+
+    def get_residual(self) -> np.ndarray:
+        out = np.empty(self.m, dtype=np.float64)
+        check(self._lib.pcdm_get_residual(self._h, out.ctypes.data, 0, current_stream()))
+        return out
+
+    def grad_backward(self, dL_dx):
+        """(dL/db [m] float64 host array, dL/dlambda) through the current iterate."""
+        g = np.ascontiguousarray(dL_dx, dtype=np.float64)
+        out = np.empty(self.m, dtype=np.float64)
+        dl = ctypes.c_double()
+        check(self._lib.pcdm_grad_backward(self._h, g.ctypes.data, out.ctypes.data, ctypes.byref(dl), 0,
+                                           current_stream()))
+        return out, dl.value
+
+
+def sample(seed: int, k: int, tau: int, n: int):
+    """S_k of the tau-nice sampler as an int32 CUDA tensor (slot order)."""
+    torch = _torch()
+    out = torch.empty(max(int(tau), 1), dtype=torch.int32, device="cuda")
+    check(load().pcdm_sample(int(seed) & (2**64 - 1), int(k), int(tau), int(n), out.data_ptr(),
+                             current_stream()))
+    return out[: int(tau)]

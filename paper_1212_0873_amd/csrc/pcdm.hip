@@ -1,0 +1,754 @@
+// pcdm.hip -- host runtime behind the C ABI of include/pcdm.h.
+//
+// Owns the device copy of the problem in the segment layout of kernels.hpp,
+// launches the step, refresh, objective and set-up kernels on the caller's
+// stream, and turns every failure into a status code plus a thread-local
+// message.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+
+#include "kernels.hpp"
+#include "pcdm.h"
+
+using namespace pcdm;
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const std::string &msg)
+{
+    t_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? PCDM_ENOMEM : PCDM_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e__ = (expr);                        \
+        if (e__ != hipSuccess)                          \
+            return hip_fail(e__, #expr);                \
+    } while (0)
+
+#define PCDM_TRY(expr)           \
+    do {                         \
+        int s__ = (expr);        \
+        if (s__ != PCDM_OK)      \
+            return s__;          \
+    } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t value_bytes(int dtype)
+{
+    switch (dtype) {
+    case PCDM_F32: return 4;
+    case PCDM_BF16: return 2;
+    case PCDM_F64: return 8;
+    default: return 0;
+    }
+}
+
+int grid_for(int64_t items, int64_t per_block, int cap)
+{
+    int64_t g = ceil_div(std::max<int64_t>(items, 1), per_block);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+constexpr int kReduceBlocks = 1024;
+
+}  // namespace
+
+struct pcdm_problem {
+    int device = 0;
+    int64_t m = 0, n = 0, nnz = 0, stored_nnz = 0, tau = 0;
+    int dtype = PCDM_F32;
+    size_t tbytes = 4;  // compute type size
+    double lambda = 0.0, beta = 1.0, atb_inf = 0.0;
+    int beta_rule = 0;
+    int64_t omega = 0;
+    uint64_t seed = 0;
+    int64_t k_host = 0;
+    int64_t refresh_every = 0;
+    int lanes = 4;
+    int lanes_auto = 1;
+    int nblk_max = 2048;
+    hipStream_t last_stream = nullptr;
+
+    char *seg = nullptr;
+    int64_t *pc = nullptr;
+    void *invL = nullptr, *x = nullptr, *r = nullptr;
+    double *r64 = nullptr, *b64 = nullptr;
+    int32_t *id_slot = nullptr;
+    void *delta_slot = nullptr;
+    int64_t slot_cap = 0;
+    Ctrl *ctrl = nullptr;
+    uint64_t *nz_part = nullptr;
+    double *part = nullptr;   // kReduceBlocks * 3
+    double *part2 = nullptr;  // nblk_max
+};
+
+namespace {
+
+void free_problem(pcdm_problem *P)
+{
+    if (!P)
+        return;
+    void *bufs[] = {P->seg, P->pc, P->invL, P->x, P->r, P->r64, P->b64, P->id_slot,
+                    P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2};
+    for (void *b : bufs)
+        if (b)
+            (void)hipFree(b);
+    delete P;
+}
+
+int compute_beta(pcdm_problem *P)
+{
+    const double om = (double)P->omega, ta = (double)P->tau, nn = (double)P->n;
+    if (P->beta_rule == 0)
+        P->beta = 1.0 + (om - 1.0) * (ta - 1.0) / std::max(1.0, nn - 1.0);
+    else if (P->beta_rule == 1)
+        P->beta = std::min(om, ta);
+    return PCDM_OK;
+}
+
+int pick_lanes(const pcdm_problem *P)
+{
+    // chunks of 4 entries per column; aim at about two chunks per lane
+    const double chunks = (double)P->stored_nnz / (4.0 * (double)P->n);
+    int g = 1;
+    while (g < 64 && 2.0 * g < chunks)
+        g *= 2;
+    return g;
+}
+
+int ensure_slots(pcdm_problem *P, int64_t tau)
+{
+    if (tau <= P->slot_cap)
+        return PCDM_OK;
+    if (P->id_slot)
+        HIP_TRY(hipFree(P->id_slot));
+    if (P->delta_slot)
+        HIP_TRY(hipFree(P->delta_slot));
+    P->id_slot = nullptr;
+    P->delta_slot = nullptr;
+    P->slot_cap = 0;
+    HIP_TRY(hipMalloc(&P->id_slot, (size_t)tau * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&P->delta_slot, (size_t)tau * P->tbytes));
+    P->slot_cap = tau;
+    return PCDM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per value type operations.
+// ---------------------------------------------------------------------------
+
+template <typename V> struct Ops {
+    using T = typename ValT<V>::T;
+
+    template <int G> static void launch_step(pcdm_problem *P, hipStream_t s)
+    {
+        const int gpb = kBlock / G;
+        const int grid = grid_for(P->tau, gpb, P->nblk_max);
+        hipLaunchKernelGGL((k_gather<V, G>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->pc,
+                           (const T *)P->r, (T *)P->x, (const T *)P->invL, P->id_slot,
+                           (T *)P->delta_slot, P->ctrl, P->nz_part, P->seed, P->tau,
+                           (uint32_t)P->n, (T)(1.0 / P->beta), (T)P->lambda);
+        hipLaunchKernelGGL((k_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->pc,
+                           (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl,
+                           P->tau);
+    }
+
+    static int step_once(pcdm_problem *P, hipStream_t s)
+    {
+        switch (P->lanes) {
+        case 1: launch_step<1>(P, s); break;
+        case 2: launch_step<2>(P, s); break;
+        case 4: launch_step<4>(P, s); break;
+        case 8: launch_step<8>(P, s); break;
+        case 16: launch_step<16>(P, s); break;
+        case 32: launch_step<32>(P, s); break;
+        case 64: launch_step<64>(P, s); break;
+        default: return fail(PCDM_EINVAL, "lanes_per_column must be a power of two <= 64");
+        }
+        return PCDM_OK;
+    }
+
+    // r64 = A x - b in float64.
+    static void residual64(pcdm_problem *P, hipStream_t s)
+    {
+        const int gm = grid_for(P->m, kBlock, P->nblk_max);
+        const int gn = grid_for(P->n, kBlock, P->nblk_max);
+        hipLaunchKernelGGL(k_neg_copy, dim3(gm), dim3(kBlock), 0, s, (const double *)P->b64, P->r64, P->m);
+        hipLaunchKernelGGL((k_refresh_cols<V>), dim3(gn), dim3(kBlock), 0, s, P->seg, P->pc,
+                           (const T *)P->x, P->r64, P->n);
+    }
+
+    static void refresh(pcdm_problem *P, hipStream_t s)
+    {
+        residual64(P, s);
+        const int gm = grid_for(P->m, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_narrow<T>), dim3(gm), dim3(kBlock), 0, s, (const double *)P->r64, (T *)P->r, P->m);
+    }
+
+    template <int G> static void launch_atr(pcdm_problem *P, const double *rv, hipStream_t s)
+    {
+        const int grid = grid_for(P->n, kBlock / G, P->nblk_max);
+        hipLaunchKernelGGL((k_atr_absmax<V, G>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->pc, rv, P->n,
+                           P->part2);
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
+                           P->ctrl->scal + 3);
+    }
+
+    // ctrl->scal[3] = max_i |a_i^T rv|
+    static int atr_absmax(pcdm_problem *P, const double *rv, hipStream_t s)
+    {
+        switch (P->lanes) {
+        case 1: launch_atr<1>(P, rv, s); break;
+        case 2: launch_atr<2>(P, rv, s); break;
+        case 4: launch_atr<4>(P, rv, s); break;
+        case 8: launch_atr<8>(P, rv, s); break;
+        case 16: launch_atr<16>(P, rv, s); break;
+        case 32: launch_atr<32>(P, rv, s); break;
+        default: launch_atr<64>(P, rv, s); break;
+        }
+        return PCDM_OK;
+    }
+
+    // ctrl->scal[0..2] = ||r64||^2, b.r64, ||x||_1
+    static void sums(pcdm_problem *P, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_obj_partials<T>), dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                           (const double *)P->r64, (const double *)P->b64, (const T *)P->x, P->m, P->n,
+                           P->part);
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part, kReduceBlocks, 3, 0,
+                           P->ctrl->scal);
+    }
+
+    static int pack(pcdm_problem *P, const int64_t *col_ptr, const int32_t *rows, const void *vals,
+                    int32_t *hist, hipStream_t s)
+    {
+        const int gn = grid_for(P->n, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_pack<V>), dim3(gn), dim3(kBlock), 0, s, col_ptr, rows, (const V *)vals,
+                           (const int64_t *)P->pc, P->n, P->m, P->seg, (T *)P->invL, hist, P->ctrl);
+        return PCDM_OK;
+    }
+};
+
+template <typename F> int dispatch(int dtype, F &&f)
+{
+    switch (dtype) {
+    case PCDM_F32: return f(Ops<float>());
+    case PCDM_BF16: return f(Ops<bf16s>());
+    case PCDM_F64: return f(Ops<double>());
+    default: return fail(PCDM_EINVAL, "unknown dtype");
+    }
+}
+
+int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, what);
+    return PCDM_OK;
+}
+
+int refresh_now(pcdm_problem *P, hipStream_t s)
+{
+    dispatch(P->dtype, [&](auto ops) {
+        decltype(ops)::refresh(P, s);
+        return PCDM_OK;
+    });
+    return check_launch("refresh");
+}
+
+std::string describe_err(uint32_t e)
+{
+    std::string out;
+    if (e & ERR_PTR) out += "col_ptr malformed (col_ptr[0] != 0, decreasing, or col_ptr[n] != nnz); ";
+    if (e & ERR_EMPTY) out += "empty column (the method needs L_i > 0); ";
+    if (e & ERR_ROW) out += "row index out of [0, m); ";
+    if (e & ERR_DUP) out += "repeated row index within a column; ";
+    if (e & ERR_NONFINITE) out += "non-finite value; ";
+    if (e & ERR_ZEROCOL) out += "column with only zero values (L_i = 0); ";
+    return out;
+}
+
+int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, uint64_t seed,
+                pcdm_problem **out)
+{
+    if (!out)
+        return fail(PCDM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A || !b)
+        return fail(PCDM_EINVAL, "A or b is NULL");
+    if (A->m < 1 || A->n < 1 || A->m > INT32_MAX || A->n > INT32_MAX - 1)
+        return fail(PCDM_EINVAL, "need 1 <= m <= 2^31 - 1 and 1 <= n <= 2^31 - 2");
+    if (A->nnz < A->n || A->nnz > (int64_t)1 << 40)
+        return fail(PCDM_EINVAL, "nnz must be >= n (no empty column) and < 2^40");
+    if (!A->col_ptr || !A->row_idx || !A->values)
+        return fail(PCDM_EINVAL, "A has a NULL array");
+    if (value_bytes(A->dtype) == 0)
+        return fail(PCDM_EINVAL, "unknown dtype");
+    if (tau < 1 || tau > A->n)
+        return fail(PCDM_EINVAL, "need 1 <= tau <= n");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda))
+        return fail(PCDM_EINVAL, "lambda must be finite and >= 0");
+
+    pcdm_problem *P = new (std::nothrow) pcdm_problem();
+    if (!P)
+        return fail(PCDM_ENOMEM, "host allocation failed");
+    struct Guard {
+        pcdm_problem *p;
+        void *tmp[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        ~Guard()
+        {
+            for (void *t : tmp)
+                if (t)
+                    (void)hipFree(t);
+            free_problem(p);
+        }
+    } guard{P};
+
+    HIP_TRY(hipGetDevice(&P->device));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device));
+    P->nblk_max = std::max(64, cus * 8);
+    P->m = A->m;
+    P->n = A->n;
+    P->nnz = A->nnz;
+    P->tau = tau;
+    P->dtype = A->dtype;
+    P->tbytes = (A->dtype == PCDM_F64) ? 8 : 4;
+    P->lambda = lambda;
+    P->seed = seed;
+    const size_t vb = value_bytes(A->dtype);
+    hipStream_t s = nullptr;
+
+    // Inputs on the device (copied there first when given on the host).
+    const int64_t *col_ptr = A->col_ptr;
+    const int32_t *rows = A->row_idx;
+    const void *vals = A->values;
+    const double *bdev = b;
+    if (!A->on_device) {
+        HIP_TRY(hipMalloc(&guard.tmp[0], (size_t)(A->n + 1) * 8));
+        HIP_TRY(hipMalloc(&guard.tmp[1], (size_t)A->nnz * 4));
+        HIP_TRY(hipMalloc(&guard.tmp[2], (size_t)A->nnz * vb));
+        HIP_TRY(hipMalloc(&guard.tmp[3], (size_t)A->m * 8));
+        HIP_TRY(hipMemcpy(guard.tmp[0], A->col_ptr, (size_t)(A->n + 1) * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(guard.tmp[1], A->row_idx, (size_t)A->nnz * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(guard.tmp[2], A->values, (size_t)A->nnz * vb, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(guard.tmp[3], b, (size_t)A->m * 8, hipMemcpyHostToDevice));
+        col_ptr = (const int64_t *)guard.tmp[0];
+        rows = (const int32_t *)guard.tmp[1];
+        vals = guard.tmp[2];
+        bdev = (const double *)guard.tmp[3];
+    }
+
+    HIP_TRY(hipMalloc(&P->ctrl, sizeof(Ctrl)));
+    HIP_TRY(hipMemset(P->ctrl, 0, sizeof(Ctrl)));
+    HIP_TRY(hipMalloc(&P->nz_part, (size_t)P->nblk_max * 8));
+    HIP_TRY(hipMemset(P->nz_part, 0, (size_t)P->nblk_max * 8));
+    HIP_TRY(hipMalloc(&P->part, (size_t)kReduceBlocks * 3 * 8));
+    HIP_TRY(hipMalloc(&P->part2, (size_t)P->nblk_max * 8));
+
+    // Padded column pointers.
+    int64_t *dpad = nullptr;
+    HIP_TRY(hipMalloc(&guard.tmp[4], (size_t)(A->n + 1) * 8));
+    dpad = (int64_t *)guard.tmp[4];
+    HIP_TRY(hipMalloc(&P->pc, (size_t)(A->n + 1) * 8));
+    {
+        const int g = grid_for(A->n + 1, kBlock, P->nblk_max);
+        hipLaunchKernelGGL(k_check_ptr, dim3(g), dim3(kBlock), 0, s, col_ptr, A->n, A->nnz, dpad, P->ctrl);
+        PCDM_TRY(check_launch("k_check_ptr"));
+        Ctrl hc;
+        HIP_TRY(hipMemcpy(&hc, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        if (hc.err)
+            return fail(PCDM_EINVAL, "invalid matrix: " + describe_err(hc.err));
+        size_t tmp_bytes = 0;
+        HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, dpad, P->pc, (int)(A->n + 1), s));
+        HIP_TRY(hipMalloc(&guard.tmp[5], std::max<size_t>(tmp_bytes, 16)));
+        HIP_TRY(hipcub::DeviceScan::ExclusiveSum(guard.tmp[5], tmp_bytes, dpad, P->pc, (int)(A->n + 1), s));
+        HIP_TRY(hipMemcpy(&P->stored_nnz, P->pc + A->n, 8, hipMemcpyDeviceToHost));
+    }
+
+    HIP_TRY(hipMalloc(&P->seg, (size_t)P->stored_nnz * (4 + vb)));
+    HIP_TRY(hipMalloc(&P->invL, (size_t)A->n * P->tbytes));
+    HIP_TRY(hipMalloc(&P->x, (size_t)A->n * P->tbytes));
+    HIP_TRY(hipMalloc(&P->r, (size_t)A->m * P->tbytes));
+    HIP_TRY(hipMalloc(&P->r64, (size_t)A->m * 8));
+    HIP_TRY(hipMalloc(&P->b64, (size_t)A->m * 8));
+    HIP_TRY(hipMemset(P->x, 0, (size_t)A->n * P->tbytes));
+    HIP_TRY(hipMemcpy(P->b64, bdev, (size_t)A->m * 8, hipMemcpyDeviceToDevice));
+    PCDM_TRY(ensure_slots(P, tau));
+
+    // Pack, L_i, row histogram.
+    {
+        int32_t *hist = nullptr;
+        HIP_TRY(hipMalloc(&hist, (size_t)A->m * 4));
+        hipError_t e = hipMemset(hist, 0, (size_t)A->m * 4);
+        int st = PCDM_OK;
+        if (e == hipSuccess)
+            st = dispatch(P->dtype, [&](auto ops) { return decltype(ops)::pack(P, col_ptr, rows, vals, hist, s); });
+        if (e == hipSuccess && st == PCDM_OK) {
+            const int g = grid_for(A->m, kBlock, P->nblk_max);
+            hipLaunchKernelGGL(k_imax_partials, dim3(g), dim3(kBlock), 0, s, (const int32_t *)hist, A->m,
+                               (int64_t *)P->part2);
+            hipLaunchKernelGGL(k_imax_final, dim3(1), dim3(kBlock), 0, s, (const int64_t *)P->part2, g, P->ctrl);
+            e = hipDeviceSynchronize();
+        }
+        (void)hipFree(hist);
+        if (e != hipSuccess)
+            return hip_fail(e, "pack");
+        PCDM_TRY(st);
+        PCDM_TRY(check_launch("k_pack"));
+        Ctrl hc;
+        HIP_TRY(hipMemcpy(&hc, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        if (hc.err)
+            return fail(PCDM_EINVAL, "invalid matrix: " + describe_err(hc.err));
+        P->omega = hc.imax;
+    }
+
+    P->lanes = pick_lanes(P);
+    P->lanes_auto = 1;
+    compute_beta(P);
+    P->refresh_every = ceil_div(P->n, P->tau);
+
+    // r = -b, ||A^T b||_inf.
+    {
+        const int gm = grid_for(A->m, kBlock, P->nblk_max);
+        hipLaunchKernelGGL(k_neg_copy, dim3(gm), dim3(kBlock), 0, s, (const double *)P->b64, P->r64, P->m);
+        PCDM_TRY(dispatch(P->dtype, [&](auto ops) {
+            using T = typename decltype(ops)::T;
+            hipLaunchKernelGGL((k_narrow<T>), dim3(gm), dim3(kBlock), 0, s, (const double *)P->r64, (T *)P->r,
+                               P->m);
+            return decltype(ops)::atr_absmax(P, P->r64, s);
+        }));
+        PCDM_TRY(check_launch("init residual"));
+        Ctrl hc;
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(&hc, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        P->atb_inf = hc.scal[3];
+    }
+    guard.p = nullptr;
+    *out = P;
+    return PCDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pcdm_last_error(void) { return t_err.c_str(); }
+
+int pcdm_create(const pcdm_csc *A, const double *b, double lambda, int64_t tau, uint64_t seed,
+                pcdm_problem **out)
+{
+    t_err.clear();
+    try {
+        return create_impl(A, b, lambda, tau, seed, out);
+    } catch (const std::exception &e) {
+        return fail(PCDM_EDEVICE, std::string("exception: ") + e.what());
+    } catch (...) {
+        return fail(PCDM_EDEVICE, "unknown exception");
+    }
+}
+
+int pcdm_destroy(pcdm_problem *h)
+{
+    if (!h)
+        return PCDM_OK;
+    hipError_t e = hipDeviceSynchronize();
+    free_problem(h);
+    if (e != hipSuccess)
+        return hip_fail(e, "pcdm_destroy");
+    return PCDM_OK;
+}
+
+int pcdm_set_option(pcdm_problem *h, const char *key, double value)
+{
+    if (!h || !key)
+        return fail(PCDM_EINVAL, "NULL handle or key");
+    const std::string k(key);
+    if (!std::isfinite(value))
+        return fail(PCDM_EINVAL, "option value must be finite");
+    if (k == "refresh_every") {
+        if (value < 0)
+            return fail(PCDM_EINVAL, "refresh_every must be >= 0");
+        h->refresh_every = (value == 0.0) ? 0 : (int64_t)value;
+    } else if (k == "beta_rule") {
+        if (value != 0.0 && value != 1.0)
+            return fail(PCDM_EINVAL, "beta_rule must be 0 (nice) or 1 (uniform)");
+        h->beta_rule = (int)value;
+        compute_beta(h);
+    } else if (k == "beta") {
+        if (!(value > 0.0))
+            return fail(PCDM_EINVAL, "beta must be > 0");
+        h->beta_rule = 2;
+        h->beta = value;
+    } else if (k == "lambda") {
+        if (!(value >= 0.0))
+            return fail(PCDM_EINVAL, "lambda must be >= 0");
+        h->lambda = value;
+    } else if (k == "tau") {
+        const int64_t t = (int64_t)value;
+        if ((double)t != value || t < 1 || t > h->n)
+            return fail(PCDM_EINVAL, "tau must be an integer in [1, n]");
+        PCDM_TRY(ensure_slots(h, t));
+        h->tau = t;
+        compute_beta(h);
+    } else if (k == "lanes_per_column") {
+        const int g = (int)value;
+        if (g == 0) {
+            h->lanes = pick_lanes(h);
+            h->lanes_auto = 1;
+        } else if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) {
+            h->lanes = g;
+            h->lanes_auto = 0;
+        } else {
+            return fail(PCDM_EINVAL, "lanes_per_column must be 0 or a power of two <= 64");
+        }
+    } else if (k == "reset_counters") {
+        hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(kBlock), 0, h->last_stream, h->nz_part,
+                           (uint64_t)0, (int64_t)h->nblk_max);
+        PCDM_TRY(check_launch("reset_counters"));
+    } else {
+        return fail(PCDM_EINVAL, "unknown option '" + k + "'");
+    }
+    return PCDM_OK;
+}
+
+int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
+{
+    if (!h || !out)
+        return fail(PCDM_EINVAL, "NULL argument");
+    hipStream_t s = h->last_stream;
+    hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(kBlock), 0, s, (const uint64_t *)h->nz_part, h->nblk_max, h->ctrl);
+    PCDM_TRY(check_launch("k_sum_u64"));
+    int64_t nz = 0;
+    HIP_TRY(hipMemcpyAsync(&nz, &h->ctrl->imax, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memset(out, 0, sizeof(*out));
+    out->m = h->m;
+    out->n = h->n;
+    out->nnz = h->nnz;
+    out->tau = h->tau;
+    out->k = h->k_host;
+    out->omega = h->omega;
+    out->refresh_every = h->refresh_every;
+    out->nonzero_updates = nz;
+    out->stored_nnz = h->stored_nnz;
+    out->beta = h->beta;
+    out->lambda = h->lambda;
+    out->atb_inf = h->atb_inf;
+    out->dtype = h->dtype;
+    out->beta_rule = h->beta_rule;
+    out->lanes_per_column = h->lanes;
+    return PCDM_OK;
+}
+
+int pcdm_step(pcdm_problem *h, int64_t nsteps, void *stream)
+{
+    if (!h)
+        return fail(PCDM_EINVAL, "NULL handle");
+    if (nsteps < 0)
+        return fail(PCDM_EINVAL, "nsteps must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    for (int64_t q = 0; q < nsteps; ++q) {
+        PCDM_TRY(dispatch(h->dtype, [&](auto ops) { return decltype(ops)::step_once(h, s); }));
+        h->k_host += 1;
+        if (h->refresh_every > 0 && h->k_host % h->refresh_every == 0)
+            PCDM_TRY(refresh_now(h, s));
+    }
+    return check_launch("pcdm_step");
+}
+
+int pcdm_objective(pcdm_problem *h, double *F, double *dual_gap, void *stream)
+{
+    if (!h || !F)
+        return fail(PCDM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    PCDM_TRY(dispatch(h->dtype, [&](auto ops) {
+        decltype(ops)::residual64(h, s);
+        decltype(ops)::sums(h, s);
+        if (dual_gap)
+            decltype(ops)::atr_absmax(h, h->r64, s);
+        return PCDM_OK;
+    }));
+    PCDM_TRY(check_launch("pcdm_objective"));
+    double sc[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(sc, h->ctrl->scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double rr = sc[0], br = sc[1], l1 = sc[2];
+    *F = 0.5 * rr + h->lambda * l1;
+    if (dual_gap) {
+        const double gmax = sc[3];
+        const double sc_theta = (gmax > h->lambda) ? h->lambda / gmax : 1.0;
+        const double D = -0.5 * sc_theta * sc_theta * rr - sc_theta * br;
+        *dual_gap = *F - D;
+    }
+    return PCDM_OK;
+}
+
+int pcdm_get_x(pcdm_problem *h, void *x_out, int32_t dtype, int32_t on_device, void *stream)
+{
+    if (!h || !x_out)
+        return fail(PCDM_EINVAL, "NULL argument");
+    if (dtype != PCDM_F32 && dtype != PCDM_F64)
+        return fail(PCDM_EINVAL, "x dtype must be PCDM_F32 or PCDM_F64");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t ob = dtype == PCDM_F64 ? 8 : 4;
+    void *dst = x_out;
+    void *tmp = nullptr;
+    if (!on_device)
+        HIP_TRY(hipMalloc(&tmp, (size_t)h->n * ob));
+    if (tmp)
+        dst = tmp;
+    const int g = grid_for(h->n, kBlock, h->nblk_max);
+    if (h->dtype == PCDM_F64) {
+        if (dtype == PCDM_F64)
+            hipLaunchKernelGGL((k_convert<double, double>), dim3(g), dim3(kBlock), 0, s, (const double *)h->x, (double *)dst, h->n);
+        else
+            hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(kBlock), 0, s, (const double *)h->x, (float *)dst, h->n);
+    } else {
+        if (dtype == PCDM_F64)
+            hipLaunchKernelGGL((k_convert<float, double>), dim3(g), dim3(kBlock), 0, s, (const float *)h->x, (double *)dst, h->n);
+        else
+            hipLaunchKernelGGL((k_convert<float, float>), dim3(g), dim3(kBlock), 0, s, (const float *)h->x, (float *)dst, h->n);
+    }
+    int st = check_launch("pcdm_get_x");
+    if (tmp) {
+        if (st == PCDM_OK) {
+            hipError_t e = hipMemcpyAsync(x_out, tmp, (size_t)h->n * ob, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                st = hip_fail(e, "pcdm_get_x copy");
+        }
+        (void)hipFree(tmp);
+    }
+    return st;
+}
+
+int pcdm_set_x(pcdm_problem *h, const void *x, int32_t dtype, int32_t on_device, int64_t k, void *stream)
+{
+    if (!h || !x)
+        return fail(PCDM_EINVAL, "NULL argument");
+    if (dtype != PCDM_F32 && dtype != PCDM_F64)
+        return fail(PCDM_EINVAL, "x dtype must be PCDM_F32 or PCDM_F64");
+    if (k < 0)
+        return fail(PCDM_EINVAL, "k must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    const size_t ib = dtype == PCDM_F64 ? 8 : 4;
+    const void *src = x;
+    void *tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&tmp, (size_t)h->n * ib));
+        hipError_t e = hipMemcpy(tmp, x, (size_t)h->n * ib, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return hip_fail(e, "pcdm_set_x copy");
+        }
+        src = tmp;
+    }
+    const int g = grid_for(h->n, kBlock, h->nblk_max);
+    if (h->dtype == PCDM_F64) {
+        if (dtype == PCDM_F64)
+            hipLaunchKernelGGL((k_convert<double, double>), dim3(g), dim3(kBlock), 0, s, (const double *)src, (double *)h->x, h->n);
+        else
+            hipLaunchKernelGGL((k_convert<float, double>), dim3(g), dim3(kBlock), 0, s, (const float *)src, (double *)h->x, h->n);
+    } else {
+        if (dtype == PCDM_F64)
+            hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(kBlock), 0, s, (const double *)src, (float *)h->x, h->n);
+        else
+            hipLaunchKernelGGL((k_convert<float, float>), dim3(g), dim3(kBlock), 0, s, (const float *)src, (float *)h->x, h->n);
+    }
+    hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(64), 0, s, &h->ctrl->k, (uint64_t)k, (int64_t)1);
+    int st = check_launch("pcdm_set_x");
+    if (st == PCDM_OK)
+        st = refresh_now(h, s);
+    if (tmp) {
+        hipError_t e = hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+        if (st == PCDM_OK && e != hipSuccess)
+            st = hip_fail(e, "pcdm_set_x sync");
+    }
+    if (st == PCDM_OK)
+        h->k_host = k;
+    return st;
+}
+
+int pcdm_get_residual(pcdm_problem *h, double *r_out, int32_t on_device, void *stream)
+{
+    if (!h || !r_out)
+        return fail(PCDM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    double *dst = r_out;
+    void *tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&tmp, (size_t)h->m * 8));
+        dst = (double *)tmp;
+    }
+    const int g = grid_for(h->m, kBlock, h->nblk_max);
+    if (h->dtype == PCDM_F64)
+        hipLaunchKernelGGL((k_widen<double>), dim3(g), dim3(kBlock), 0, s, (const double *)h->r, dst, h->m);
+    else
+        hipLaunchKernelGGL((k_widen<float>), dim3(g), dim3(kBlock), 0, s, (const float *)h->r, dst, h->m);
+    int st = check_launch("pcdm_get_residual");
+    if (tmp) {
+        if (st == PCDM_OK) {
+            hipError_t e = hipMemcpyAsync(r_out, tmp, (size_t)h->m * 8, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                st = hip_fail(e, "pcdm_get_residual copy");
+        }
+        (void)hipFree(tmp);
+    }
+    return st;
+}
+
+int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db, double *dL_dlambda,
+                       int32_t on_device, void *stream)
+{
+    (void)dL_dx;
+    (void)dL_db;
+    (void)dL_dlambda;
+    (void)on_device;
+    (void)stream;
+    if (!h)
+        return fail(PCDM_EINVAL, "NULL handle");
+    return fail(PCDM_ESTATE, "pcdm_grad_backward: not available in this build");
+}
+
+int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device, void *stream)
+{
+    if (!out_device)
+        return fail(PCDM_EINVAL, "NULL output");
+    if (n < 1 || n > INT32_MAX || tau < 0 || tau > n)
+        return fail(PCDM_EINVAL, "need 1 <= n <= 2^31-1 and 0 <= tau <= n");
+    if (tau == 0)
+        return PCDM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int g = grid_for(tau, kBlock, 4096);
+    hipLaunchKernelGGL(k_sample, dim3(g), dim3(kBlock), 0, s, seed, k, tau, (uint32_t)n, out_device);
+    return check_launch("pcdm_sample");
+}
+
+}  // extern "C"

@@ -9,6 +9,7 @@ from .lasso import (  # noqa: F401
     CSC,
     LassoInstance,
     random_csc,
+    random_csc_ragged,
     planted_lasso,
     tightness_matrix,
     separable_matrix,

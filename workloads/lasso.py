@@ -257,3 +257,23 @@ def orthonormal_block_hadamard(nblocks: int, bsize: int, rng: Optional[np.random
     if rng is not None:
         M = M[rng.permutation(n)][:, rng.permutation(n)]
     return dense_to_csc(M)
+
+
+def random_csc_ragged(m: int, n: int, dmin: int, dmax: int, rng: np.random.Generator,
+                      normalize: bool = False, dtype: str = "f64", shuffle_rows: bool = True) -> CSC:
+    """Column degrees uniform in [dmin, dmax] (distinct rows, N(0,1) values).
+    ``shuffle_rows`` stores each column's rows in random order (CSC allows any
+    order within a column)."""
+    degs = rng.integers(dmin, dmax + 1, size=n)
+    col_ptr = np.zeros(n + 1, dtype=np.int64)
+    col_ptr[1:] = np.cumsum(degs)
+    rows = np.empty(int(col_ptr[-1]), dtype=np.int32)
+    vals = rng.standard_normal(int(col_ptr[-1]))
+    for i in range(n):
+        s, e = col_ptr[i], col_ptr[i + 1]
+        r = rng.choice(m, size=int(degs[i]), replace=False)
+        rows[s:e] = r if shuffle_rows else np.sort(r)
+        if normalize:
+            vals[s:e] /= np.linalg.norm(vals[s:e])
+    A = CSC(m, n, col_ptr, rows, vals)
+    return A if dtype == "f64" else A.astype(dtype)
