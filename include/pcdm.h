@@ -52,12 +52,13 @@ typedef enum {
 } pcdm_status;
 
 /* Value types.  The dtype of A's values selects the arithmetic:
- *   PCDM_F64  : values, x and r in float64, float64 sums;
- *   PCDM_F32  : values, x and r in float32, float32 dot products;
- *   PCDM_BF16 : values stored as bfloat16 (raw uint16 bit patterns), x and r
- *               in float32, float32 dot products.
- * In every mode the periodic residual refresh r = A x - b, the objective and
- * the duality gap are computed in float64. */
+ *   PCDM_F64  : values and r in float64, float64 sums;
+ *   PCDM_F32  : values and r in float32, float32 dot products;
+ *   PCDM_BF16 : values stored as bfloat16 (raw uint16 bit patterns), r in
+ *               float32, float32 dot products.
+ * In every mode x, 1/L_i and the update of x_i are float64, and the periodic
+ * residual refresh r = A x - b, the objective and the duality gap are
+ * computed in float64. */
 typedef enum { PCDM_F32 = 0, PCDM_BF16 = 1, PCDM_F64 = 2 } pcdm_dtype;
 
 /* Compressed sparse column matrix; column i holds coordinate i's data a_i
@@ -95,8 +96,8 @@ typedef struct pcdm_info {
     int32_t dtype;
     int32_t beta_rule;       /* 0 = tau-nice, 1 = tau-uniform min(omega,tau),     */
                              /* 2 = explicit value set with option "beta"         */
-    int32_t lanes_per_column;/* step-kernel schedule in use                      */
-    int32_t reserved;
+    int32_t lanes_per_column;/* step-kernel schedule: lanes reading one column    */
+    int32_t chunks_per_lane; /* ... and 4-entry chunks each lane holds          */
 } pcdm_info;
 
 /*
@@ -106,7 +107,8 @@ typedef struct pcdm_info {
  *   lambda  : >= 0 and finite;
  *   tau     : sampled coordinates per step, 1 <= tau <= n;
  *   seed    : key of the tau-nice sampler (S_k depends on (seed, k) only).
- * Requires 1 <= m <= 2^31 - 1 and 1 <= n <= 2^31 - 2.  Rejects (PCDM_EINVAL) empty or all-zero
+ * Requires 1 <= n <= 2^31 - 2 and 1 <= m with the working residual under
+ * 4 GiB (m < 2^30 for PCDM_F32/PCDM_BF16, m < 2^29 for PCDM_F64).  Rejects (PCDM_EINVAL) empty or all-zero
  * columns (the paper assumes L_i > 0), repeated rows in a column, rows out
  * of range, non-finite values, a malformed col_ptr.  x starts at 0 and
  * r = -b.  Runs on the default stream and returns after the device work is
@@ -131,7 +133,13 @@ const char *pcdm_last_error(void);
  *   "tau"              new tau in [1, n] (beta recomputed by the rule);
  *   "lanes_per_column" 0 = automatic, or 1, 2, 4, 8, 16, 32, 64 lanes
  *                      cooperating on one sampled column;
- *   "reset_counters"   any value: zero nonzero_updates.
+ *   "chunks_per_lane"  0 = automatic, or 1, 2, 4 four-entry chunks of the
+ *                      column each lane keeps in registers; supported pairs
+ *                      (lanes, chunks): (1|2, 1|2|4), (4|8, 1|2), (16|32|64, 1);
+ *   "reset_counters"   any value: zero nonzero_updates;
+ *   "kernel_timing"    1 = record HIP events around every step-kernel launch
+ *                      (see pcdm_kernel_time), 0 = stop; either value first
+ *                      zeroes the accumulated times.
  * Unknown keys and out-of-range values give PCDM_EINVAL.
  */
 int pcdm_set_option(pcdm_problem *h, const char *key, double value);
@@ -181,6 +189,16 @@ int pcdm_get_residual(pcdm_problem *h, double *r_out, int32_t on_device, void *s
  */
 int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db,
                        double *dL_dlambda, int32_t on_device, void *stream);
+
+/*
+ * Device time of one kernel kind of the step while option "kernel_timing" is
+ * on: kernel = "gather" (sample, partial derivatives, update of x),
+ * "scatter" (residual scatter-add) or "refresh" (float64 residual refresh).
+ * Measured between HIP events recorded on the launch stream just before and
+ * after each launch.  Waits for the recorded launches; writes the number of
+ * launches and their summed milliseconds since timing was (re)started.
+ */
+int pcdm_kernel_time(pcdm_problem *h, const char *kernel, int64_t *launches, double *total_ms);
 
 /*
  * The tau-nice sampler on its own: writes S_k = {pi_k(j) : 0 <= j < tau}

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "PCDM_OK", -1: "PCDM_EINVAL", -2: "PCDM_ENOMEM", -3: "PCDM_ED
 # every symbol include/pcdm.h declares
 EXPORTS = ("pcdm_create", "pcdm_destroy", "pcdm_last_error", "pcdm_set_option", "pcdm_get_info",
            "pcdm_step", "pcdm_objective", "pcdm_get_x", "pcdm_set_x", "pcdm_get_residual",
-           "pcdm_grad_backward", "pcdm_sample")
+           "pcdm_grad_backward", "pcdm_kernel_time", "pcdm_sample")
 
 
 class pcdm_csc(ctypes.Structure):
@@ -32,7 +32,7 @@ class pcdm_info(ctypes.Structure):
                 ("refresh_every", ctypes.c_int64), ("nonzero_updates", ctypes.c_int64),
                 ("stored_nnz", ctypes.c_int64), ("beta", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("atb_inf", ctypes.c_double), ("dtype", ctypes.c_int32), ("beta_rule", ctypes.c_int32),
-                ("lanes_per_column", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lanes_per_column", ctypes.c_int32), ("chunks_per_lane", ctypes.c_int32)]
 
 
 class PCDMError(RuntimeError):
@@ -69,6 +69,7 @@ def load() -> ctypes.CDLL:
             "pcdm_get_residual": [vp, vp, i32, vp],
             "pcdm_grad_backward": [vp, vp, vp, pd, i32, vp],
             "pcdm_sample": [u64, u64, i64, i64, vp, vp],
+            "pcdm_kernel_time": [vp, ctypes.c_char_p, ctypes.POINTER(i64), pd],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)

@@ -119,6 +119,13 @@ class Problem:
         d["lambda"] = d.pop("lambda_")
         return d
 
+    def kernel_time(self, kernel: str):
+        """(launches, total milliseconds) of one kernel kind while timing is on."""
+        n = ctypes.c_int64()
+        t = ctypes.c_double()
+        check(self._lib.pcdm_kernel_time(self._h, kernel.encode(), ctypes.byref(n), ctypes.byref(t)))
+        return n.value, t.value
+
     # -- state ------------------------------------------------------------------
     def get_x(self, dtype=np.float64) -> np.ndarray:
         out = np.empty(self.n, dtype=dtype)

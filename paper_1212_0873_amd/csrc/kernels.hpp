@@ -1,16 +1,25 @@
 // kernels.hpp -- gfx950 kernels of the synchronous PCDM1 step on the LASSO.
 //
 // Device layout (built once by k_pack):
-//   seg     : column segments.  Column i starts at entry offset pc[i] (a
-//             multiple of 4) and holds dpad_i = pc[i+1] - pc[i] entries
-//             (its nonzeros rounded up to a multiple of 4): first dpad_i int32
-//             row indices, then dpad_i values of type V.  One sampled column
-//             is therefore one contiguous byte range, read with 16-byte (8-byte
-//             for bf16) vector loads.  Padding entries repeat the column's last
-//             row with value 0, so they add nothing to a dot product and are
-//             skipped by the scatter.
-//   invL    : 1 / L_i, L_i = ||a_i||^2 summed in float64 from stored values.
-//   x, r    : iterate and working residual r = A x - b in the compute type T.
+//   seg  : one contiguous record per column i (coordinate i):
+//            [ x_i : f64 ][ 1/L_i : f64 ][ dpad_i rows : int32 ][ dpad_i values : V ]
+//          dpad_i = the column's nonzeros rounded up to a multiple of 4.
+//          Padding entries repeat the column's last row with value 0: they add
+//          nothing to a dot product and the scatter skips them.  A sampled
+//          coordinate's whole update (x_i, 1/L_i, its rows and values) is one
+//          contiguous read, so a random column costs its own bytes and no
+//          separate random lines for x, 1/L or a pointer array.
+//          Record offset: when every column has the same dpad (the usual
+//          fixed-degree case) it is i * stride and no pointer array is read;
+//          otherwise pc[i] * (4 + sizeof(V)) + 16 i, with pc the padded column
+//          pointers.
+//   x    : dense float64 mirror of the x_i held in the records, written with
+//          them, read by the column-ordered passes (refresh, objective).
+//          x is float64 on every path: a damped step (1/beta of the
+//          coordinate-minimising step) below half a float32 ulp of x_i would
+//          be lost, and the iteration would stall at a KKT residual near
+//          beta L_i ulp(x_i).  1/L_i = 1/||a_i||^2 is summed in float64.
+//   r    : working residual r = A x - b in the compute type T.
 //   id_slot, delta_slot : per step, slot j's coordinate and its update.
 //
 // One step = k_gather (sample, gather-dot, prox, write x) followed by
@@ -28,6 +37,30 @@
 namespace pcdm {
 
 constexpr int kBlock = 256;
+constexpr int kHeader = 16;  // bytes of {x_i, 1/L_i} in front of each column
+
+// Column chunks (4 entries) a gather lane keeps in flight before its first
+// dependent r load: more hides latency, fewer leaves registers for more waves.
+#ifndef PCDM_CHUNK_BUDGET
+#define PCDM_CHUNK_BUDGET 8
+#endif
+// 1: column records are read with non-temporal loads (streamed past the
+// caches, which then keep r).
+#ifndef PCDM_NT_RECORDS
+#define PCDM_NT_RECORDS 0
+#endif
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+template <typename T> __device__ __forceinline__ T ld_rec(const T *p)
+{
+#if PCDM_NT_RECORDS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 struct bf16s {
     uint16_t bits;
@@ -35,11 +68,11 @@ struct bf16s {
 
 // Device control block (one per problem).
 struct Ctrl {
-    uint64_t k;        // steps taken: key of the next step's sample
-    uint32_t err;      // validation flags written at create
-    uint32_t pad0;
-    double scal[8];    // reduction results
-    int64_t imax;      // integer reduction result
+    uint64_t k;           // steps taken: key of the next step's sample
+    uint32_t err;         // validation flags written at create
+    uint32_t nonuniform;  // set when padded column lengths differ
+    double scal[8];       // reduction results
+    int64_t imax;         // integer reduction result
 };
 
 enum : uint32_t {
@@ -62,39 +95,59 @@ __device__ __forceinline__ float widen(bf16s v) { return __uint_as_float(((uint3
 
 template <typename V> constexpr int entry_bytes() { return 4 + (int)sizeof(V); }
 
-// Load entries e..e+3 of a column (e a multiple of 4).
+// Where column records live.
+struct Layout {
+    const int64_t *pc;  // padded column pointers (entries), used when fixed_dpad == 0
+    int64_t fixed_dpad; // common padded length, or 0
+    int64_t stride;     // record bytes when fixed_dpad != 0
+};
+
+template <typename V>
+__device__ __forceinline__ void locate(const Layout &L, int64_t i, int64_t &off, int32_t &dp)
+{
+    if (L.fixed_dpad) {
+        dp = (int32_t)L.fixed_dpad;
+        off = i * L.stride;
+    } else {
+        const int64_t p0 = L.pc[i];
+        dp = (int32_t)(L.pc[i + 1] - p0);
+        off = p0 * entry_bytes<V>() + (int64_t)kHeader * i;
+    }
+}
+
+// Load entries e..e+3 of a column whose rows start at `rows` (e a multiple of 4).
 template <typename V> struct Chunk4;
 
 template <> struct Chunk4<float> {
-    __device__ __forceinline__ static void load(const char *col, int64_t dpad, int64_t e, int (&rw)[4],
+    __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
                                                 float (&v)[4])
     {
-        const int4 a = *reinterpret_cast<const int4 *>(col + 4 * e);
-        const float4 b = *reinterpret_cast<const float4 *>(col + 4 * dpad + 4 * e);
+        const v4i_t a = ld_rec(reinterpret_cast<const v4i_t *>(rows + 4 * e));
+        const v4f_t b = ld_rec(reinterpret_cast<const v4f_t *>(rows + 4 * dpad + 4 * e));
         rw[0] = a.x; rw[1] = a.y; rw[2] = a.z; rw[3] = a.w;
         v[0] = b.x; v[1] = b.y; v[2] = b.z; v[3] = b.w;
     }
 };
 
 template <> struct Chunk4<double> {
-    __device__ __forceinline__ static void load(const char *col, int64_t dpad, int64_t e, int (&rw)[4],
+    __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
                                                 double (&v)[4])
     {
-        const int4 a = *reinterpret_cast<const int4 *>(col + 4 * e);
-        const double2 b0 = *reinterpret_cast<const double2 *>(col + 4 * dpad + 8 * e);
-        const double2 b1 = *reinterpret_cast<const double2 *>(col + 4 * dpad + 8 * e + 16);
+        const int4 a = *reinterpret_cast<const int4 *>(rows + 4 * e);
+        const double2 b0 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e);
+        const double2 b1 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e + 16);
         rw[0] = a.x; rw[1] = a.y; rw[2] = a.z; rw[3] = a.w;
         v[0] = b0.x; v[1] = b0.y; v[2] = b1.x; v[3] = b1.y;
     }
 };
 
 template <> struct Chunk4<bf16s> {
-    __device__ __forceinline__ static void load(const char *col, int64_t dpad, int64_t e, int (&rw)[4],
+    __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
                                                 float (&v)[4])
     {
-        const int2 a0 = *reinterpret_cast<const int2 *>(col + 4 * e);
-        const int2 a1 = *reinterpret_cast<const int2 *>(col + 4 * e + 8);
-        const uint2 b = *reinterpret_cast<const uint2 *>(col + 4 * dpad + 2 * e);
+        const int2 a0 = *reinterpret_cast<const int2 *>(rows + 4 * e);
+        const int2 a1 = *reinterpret_cast<const int2 *>(rows + 4 * e + 8);
+        const uint2 b = *reinterpret_cast<const uint2 *>(rows + 4 * dpad + 2 * e);
         rw[0] = a0.x; rw[1] = a0.y; rw[2] = a1.x; rw[3] = a1.y;
         v[0] = __uint_as_float(b.x << 16);
         v[1] = __uint_as_float(b.x & 0xFFFF0000u);
@@ -115,6 +168,13 @@ template <typename T> __device__ __forceinline__ void atomic_add_hw(T *p, T v)
     unsafeAtomicAdd(p, v);
 }
 
+// base[row] through a 32-bit byte offset from a uniform base (the host
+// checks that r spans < 4 GiB).
+template <typename T> __device__ __forceinline__ T load_row(const T *__restrict__ base, int row)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (uint32_t)row * (uint32_t)sizeof(T));
+}
+
 // Sum over the G lanes of a group (G a power of two, groups aligned).
 template <int G, typename T> __device__ __forceinline__ T group_sum(T v)
 {
@@ -124,9 +184,8 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
-template <typename T> __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *lds)
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *lds)
 {
-    // wave reduce then LDS
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         v += __shfl_xor(v, o, 64);
@@ -142,63 +201,172 @@ template <typename T> __device__ __forceinline__ uint64_t block_sum_u64(uint64_t
 }
 
 // --------------------------------------------------------------------------
+// Tiles.  A wave owns 64 consecutive slots (or columns).  Per-slot work
+// (sampling, locating the record, x_i and 1/L_i, the update) runs one lane
+// per slot; the column entries are then read in G rounds, each round giving
+// 64/G columns to groups of G lanes, so a column's contiguous entries are read
+// by G neighbouring lanes with 16-byte loads.  Each lane holds C chunks (4
+// entries each) of its round's column in registers, with the loads of a
+// batch of rounds issued before any dependent gather; longer columns finish
+// in a loop.
+// --------------------------------------------------------------------------
+
+template <int G> struct TileLanes {
+    static constexpr int CPR = 64 / G;  // columns per round
+    int lane, gl, grp;
+    __device__ __forceinline__ TileLanes()
+    {
+        lane = threadIdx.x & 63;
+        gl = lane & (G - 1);
+        grp = lane / G;
+    }
+    // lane owning the column handled by this lane's group in round q
+    __device__ __forceinline__ int owner(int q) const { return q * CPR + grp; }
+    // in round q, the group leader of column `lane` (valid when lane / CPR == q)
+    __device__ __forceinline__ int leader_of_mine(int q) const { return ((lane - q * CPR) & (CPR - 1)) * G; }
+};
+
+__device__ __forceinline__ int64_t wave_global_id() { return (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); }
+__device__ __forceinline__ int64_t wave_count() { return (int64_t)gridDim.x * (kBlock / 64); }
+
+// For every live column of a tile (owner lanes give the record offset and
+// length; dp = 0 means nothing to do) call f(q, wq, row, value) on each
+// stored entry, where wq is the owner's scalar w broadcast to its group.
+template <typename V, int G, typename W, typename F>
+__device__ __forceinline__ void tile_entries(const char *__restrict__ seg, const TileLanes<G> &tl, int64_t off,
+                                             int32_t dp, W w, F &&f)
+{
+    using T = typename ValT<V>::T;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const int64_t coff = __shfl(off, tl.owner(q));
+        const int32_t cdp = __shfl(dp, tl.owner(q));
+        const W wq = __shfl(w, tl.owner(q));
+        const char *rows = seg + coff + kHeader;
+        for (int e = 4 * tl.gl; e < cdp; e += 4 * G) {
+            int rw[4];
+            T v[4];
+            Chunk4<V>::load(rows, cdp, e, rw, v);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                f(q, wq, rw[t], v[t]);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // The step.
 // --------------------------------------------------------------------------
 
-// Phase 1 of step k: for each slot j < tau (G lanes per slot) take
-// i = pi_k(j), g_i = a_i^T r, the damped soft-threshold update of x_i, and
-// record (i, delta_i) in slot j.
-template <typename V, int G>
+// Phase 1 of step k: slot j < tau takes i = pi_k(j), g_i = a_i^T r (working
+// precision T) and the damped soft-threshold update of x_i in float64;
+// records (i, delta_i) in slot j and writes x_i (record and mirror).
+template <typename V, int G, int C>
 __global__ void __launch_bounds__(kBlock)
-k_gather(const char *__restrict__ seg, const int64_t *__restrict__ pc,
-         const typename ValT<V>::T *__restrict__ r, typename ValT<V>::T *__restrict__ x,
-         const typename ValT<V>::T *__restrict__ invL, int32_t *__restrict__ id_slot,
-         typename ValT<V>::T *__restrict__ delta_slot, const Ctrl *__restrict__ ctrl,
-         uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau, uint32_t n,
-         typename ValT<V>::T inv_beta, typename ValT<V>::T lam)
+k_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
+         double *__restrict__ xm, int32_t *__restrict__ id_slot, typename ValT<V>::T *__restrict__ delta_slot,
+         const Ctrl *__restrict__ ctrl, uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau,
+         uint32_t n, double inv_beta, double lam)
 {
     using T = typename ValT<V>::T;
-    constexpr int EB = entry_bytes<V>();
     __shared__ uint32_t s_keys[kNiceRounds];
     __shared__ uint64_t s_red[kBlock / 64];
 
     const NiceKey key = nice_key_block(seed, ctrl->k, n, s_keys);
-    const int lane = threadIdx.x & (G - 1);
-    const int64_t groups_per_block = kBlock / G;
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+    const TileLanes<G> tl;
     uint64_t nz = 0;
 
-    for (int64_t slot = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / G; slot < tau;
-         slot += stride) {
-        const uint32_t i = nice_slot((uint32_t)slot, key);
-        const int64_t p0 = pc[i];
-        const int64_t dpad = pc[i + 1] - p0;
-        const char *col = seg + p0 * EB;
-        T acc = T(0);
-        for (int64_t e = 4 * lane; e < dpad; e += 4 * G) {
-            int rw[4];
-            T v[4];
-            Chunk4<V>::load(col, dpad, e, rw, v);
-            acc += v[0] * r[rw[0]];
-            acc += v[1] * r[rw[1]];
-            acc += v[2] * r[rw[2]];
-            acc += v[3] * r[rw[3]];
+    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64) {
+        const int64_t slot = base + tl.lane;
+        const bool act = slot < tau;
+        uint32_t i = 0;
+        int64_t off = 0;
+        int32_t dp = 0;
+        double xi = 0.0, il = 0.0;
+        if (act) {
+            i = nice_slot((uint32_t)slot, key);
+            locate<V>(lay, i, off, dp);
+            const double *hdr = reinterpret_cast<const double *>(seg + off);
+            xi = hdr[0];
+            il = hdr[1];
         }
-        acc = group_sum<G>(acc);
-        if (lane == 0) {
-            const T xi = x[i];
-            const T scale = invL[i] * inv_beta;  // 1 / (beta L_i)
-            const T xn = soft_threshold<T>(xi - acc * scale, lam * scale);
-            const T d = xn - xi;
+        // rounds in batches of RB so that at most 8 chunks per lane are live
+        constexpr int RB = (G < PCDM_CHUNK_BUDGET / C) ? G : (PCDM_CHUNK_BUDGET / C > 0 ? PCDM_CHUNK_BUDGET / C : 1);
+        T mine = T(0);
+#pragma unroll(G == RB ? 1 : 2)
+        for (int q0 = 0; q0 < G; q0 += RB) {
+            int64_t qoff[RB];
+            int32_t qdp[RB];
+            int rw[RB][C][4];
+            T v[RB][C][4];
+#pragma unroll
+            for (int qq = 0; qq < RB; ++qq) {
+                const int q = q0 + qq;
+                qoff[qq] = __shfl(off, tl.owner(q));
+                qdp[qq] = __shfl(dp, tl.owner(q));
+                const char *rows = seg + qoff[qq] + kHeader;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int e = 4 * (tl.gl + G * c);
+                    if (e < qdp[qq]) {
+                        Chunk4<V>::load(rows, qdp[qq], e, rw[qq][c], v[qq][c]);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            rw[qq][c][t] = 0;
+                            v[qq][c][t] = T(0);
+                        }
+                    }
+                }
+            }
+            T acc[RB];
+#pragma unroll
+            for (int qq = 0; qq < RB; ++qq) {
+                acc[qq] = T(0);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    if (4 * (tl.gl + G * c) < qdp[qq]) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[qq] += v[qq][c][t] * load_row(r, rw[qq][c][t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int qq = 0; qq < RB; ++qq) {
+                const char *rows = seg + qoff[qq] + kHeader;
+                for (int e = 4 * (tl.gl + G * C); e < qdp[qq]; e += 4 * G) {
+                    int rr[4];
+                    T vv[4];
+                    Chunk4<V>::load(rows, qdp[qq], e, rr, vv);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[qq] += vv[t] * load_row(r, rr[t]);
+                }
+            }
+#pragma unroll
+            for (int qq = 0; qq < RB; ++qq) {
+                const int q = q0 + qq;
+                const T sum = group_sum<G>(acc[qq]);
+                const T got = __shfl(sum, tl.leader_of_mine(q));
+                if (tl.lane / TileLanes<G>::CPR == q)
+                    mine = got;
+            }
+        }
+        if (act) {
+            const double scale = il * inv_beta;  // 1 / (beta L_i)
+            const double xn = soft_threshold<double>(xi - (double)mine * scale, lam * scale);
+            const double d = xn - xi;
             id_slot[slot] = (int32_t)i;
-            delta_slot[slot] = d;
-            if (d != T(0)) {
-                x[i] = xn;
+            delta_slot[slot] = (T)d;
+            if (d != 0.0) {
+                *reinterpret_cast<double *>(seg + off) = xn;
+                xm[i] = xn;
                 ++nz;
             }
         }
     }
-    const uint64_t tot = block_sum_u64<T>(nz, s_red);
+    const uint64_t tot = block_sum_u64(nz, s_red);
     if (threadIdx.x == 0 && tot)
         nz_part[blockIdx.x] += tot;
 }
@@ -208,35 +376,28 @@ k_gather(const char *__restrict__ seg, const int64_t *__restrict__ pc,
 // a row).  Also advances the step counter for step k+1.
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
-k_scatter(const char *__restrict__ seg, const int64_t *__restrict__ pc,
-          typename ValT<V>::T *__restrict__ r, const int32_t *__restrict__ id_slot,
-          const typename ValT<V>::T *__restrict__ delta_slot, Ctrl *__restrict__ ctrl, int64_t tau)
+k_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restrict__ r,
+          const int32_t *__restrict__ id_slot, const typename ValT<V>::T *__restrict__ delta_slot,
+          Ctrl *__restrict__ ctrl, int64_t tau)
 {
     using T = typename ValT<V>::T;
-    constexpr int EB = entry_bytes<V>();
     if (blockIdx.x == 0 && threadIdx.x == 0)
         ctrl->k += 1;  // no block of this kernel reads k
-    const int lane = threadIdx.x & (G - 1);
-    const int64_t groups_per_block = kBlock / G;
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
-    for (int64_t slot = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / G; slot < tau;
-         slot += stride) {
-        const T d = delta_slot[slot];
-        if (d == T(0))
+    const TileLanes<G> tl;
+    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64) {
+        const int64_t slot = base + tl.lane;
+        const T d = slot < tau ? delta_slot[slot] : T(0);
+        const bool live = d != T(0);
+        if (!__any(live))
             continue;
-        const int32_t i = id_slot[slot];
-        const int64_t p0 = pc[i];
-        const int64_t dpad = pc[i + 1] - p0;
-        const char *col = seg + p0 * EB;
-        for (int64_t e = 4 * lane; e < dpad; e += 4 * G) {
-            int rw[4];
-            T v[4];
-            Chunk4<V>::load(col, dpad, e, rw, v);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (v[q] != T(0))
-                    atomic_add_hw<T>(r + rw[q], d * v[q]);
-        }
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (live)
+            locate<V>(lay, id_slot[slot], off, dp);
+        tile_entries<V, G>(seg, tl, off, dp, d, [&](int, T dq, int row, T val) {
+            if (val != T(0))
+                atomic_add_hw<T>(r + row, dq * val);
+        });
     }
 }
 
@@ -261,29 +422,41 @@ k_neg_copy(const double *__restrict__ b, double *__restrict__ r64, int64_t m)
         r64[j] = -b[j];
 }
 
-// r64 += x_i a_i for x_i != 0 (float64 atomics).
+// r64 += x_i a_i for x_i != 0 (float64 atomics); tiles of 64 consecutive columns.
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_refresh_cols(const char *__restrict__ seg, Layout lay, const double *__restrict__ xm,
+               double *__restrict__ r64, int64_t n)
+{
+    using T = typename ValT<V>::T;
+    const TileLanes<G> tl;
+    for (int64_t base = wave_global_id() * 64; base < n; base += wave_count() * 64) {
+        const int64_t col = base + tl.lane;
+        const double xi = col < n ? xm[col] : 0.0;
+        const bool live = xi != 0.0;
+        if (!__any(live))
+            continue;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (live)
+            locate<V>(lay, col, off, dp);
+        tile_entries<V, G>(seg, tl, off, dp, xi, [&](int, double xq, int row, T val) {
+            if (val != T(0))
+                atomic_add_hw<double>(r64 + row, xq * (double)val);
+        });
+    }
+}
+
+// Copy the dense x mirror into the column records (after pcdm_set_x).
 template <typename V>
 __global__ void __launch_bounds__(kBlock)
-k_refresh_cols(const char *__restrict__ seg, const int64_t *__restrict__ pc,
-               const typename ValT<V>::T *__restrict__ x, double *__restrict__ r64, int64_t n)
+k_x_to_records(char *__restrict__ seg, Layout lay, const double *__restrict__ xm, int64_t n)
 {
-    constexpr int EB = entry_bytes<V>();
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        const double xi = (double)x[i];
-        if (xi == 0.0)
-            continue;
-        const int64_t p0 = pc[i];
-        const int64_t dpad = pc[i + 1] - p0;
-        const char *col = seg + p0 * EB;
-        for (int64_t e = 0; e < dpad; e += 4) {
-            int rw[4];
-            typename ValT<V>::T v[4];
-            Chunk4<V>::load(col, dpad, e, rw, v);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (v[q] != 0)
-                    atomic_add_hw<double>(r64 + rw[q], xi * (double)v[q]);
-        }
+        int64_t off;
+        int32_t dp;
+        locate<V>(lay, i, off, dp);
+        *reinterpret_cast<double *>(seg + off) = xm[i];
     }
 }
 
@@ -352,9 +525,8 @@ __device__ __forceinline__ double block_max_f64(double v, double *lds)
 }
 
 // part[3*blk + {0,1,2}] = partial sums of r64^2, b.r64, |x|.
-template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_obj_partials(const double *__restrict__ r64, const double *__restrict__ b, const T *__restrict__ x,
+k_obj_partials(const double *__restrict__ r64, const double *__restrict__ b, const double *__restrict__ xm,
                int64_t m, int64_t n, double *__restrict__ part)
 {
     __shared__ double lds[kBlock];
@@ -366,7 +538,7 @@ k_obj_partials(const double *__restrict__ r64, const double *__restrict__ b, con
         br += b[j] * v;
     }
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        ax += fabs((double)x[i]);
+        ax += fabs(xm[i]);
     rr = block_sum_f64(rr, lds);
     br = block_sum_f64(br, lds);
     ax = block_sum_f64(ax, lds);
@@ -377,13 +549,13 @@ k_obj_partials(const double *__restrict__ r64, const double *__restrict__ b, con
     }
 }
 
-// out[c] = sum_b part[ncomp*b + c] (c < ncomp) or max for mode 1; one block.
+// out[c] = sum (mode 0) or max (mode 1) over q of part[ncomp*q + c]; one block.
 __global__ void __launch_bounds__(kBlock)
 k_final(const double *__restrict__ part, int nparts, int ncomp, int mode, double *__restrict__ out)
 {
     __shared__ double lds[kBlock];
     for (int c = 0; c < ncomp; ++c) {
-        double a = mode ? 0.0 : 0.0;
+        double a = 0.0;
         for (int q = threadIdx.x; q < nparts; q += kBlock)
             a = mode ? fmax(a, part[ncomp * q + c]) : a + part[ncomp * q + c];
         a = mode ? block_max_f64(a, lds) : block_sum_f64(a, lds);
@@ -392,33 +564,39 @@ k_final(const double *__restrict__ part, int nparts, int ncomp, int mode, double
     }
 }
 
-// part[blk] = max over the block's columns of |a_i^T r64| (float64 sums).
+// part[blk] = max over the block's columns of |a_i^T r64| (float64 sums);
+// tiles of 64 consecutive columns, so the records stream.
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
-k_atr_absmax(const char *__restrict__ seg, const int64_t *__restrict__ pc, const double *__restrict__ r64,
-             int64_t n, double *__restrict__ part)
+k_atr_absmax(const char *__restrict__ seg, Layout lay, const double *__restrict__ r64, int64_t n,
+             double *__restrict__ part)
 {
-    constexpr int EB = entry_bytes<V>();
+    using T = typename ValT<V>::T;
     __shared__ double lds[kBlock];
-    const int lane = threadIdx.x & (G - 1);
-    const int64_t groups_per_block = kBlock / G;
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+    const TileLanes<G> tl;
     double best = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * groups_per_block + threadIdx.x / G; i < n; i += stride) {
-        const int64_t p0 = pc[i];
-        const int64_t dpad = pc[i + 1] - p0;
-        const char *col = seg + p0 * EB;
-        double acc = 0.0;
-        for (int64_t e = 4 * lane; e < dpad; e += 4 * G) {
-            int rw[4];
-            typename ValT<V>::T v[4];
-            Chunk4<V>::load(col, dpad, e, rw, v);
+    for (int64_t base = wave_global_id() * 64; base < n; base += wave_count() * 64) {
+        const int64_t col = base + tl.lane;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (col < n)
+            locate<V>(lay, col, off, dp);
+        double acc[G];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                acc += (double)v[q] * r64[rw[q]];
+        for (int q = 0; q < G; ++q)
+            acc[q] = 0.0;
+        tile_entries<V, G>(seg, tl, off, dp, 0, [&](int q, int, int row, T val) {
+            acc[q] += (double)val * r64[row];
+        });
+        double mine = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double s = group_sum<G>(acc[q]);
+            const double got = __shfl(s, tl.leader_of_mine(q));
+            if (tl.lane / TileLanes<G>::CPR == q)
+                mine = got;
         }
-        acc = group_sum<G>(acc);
-        best = fmax(best, fabs(acc));
+        best = fmax(best, fabs(mine));
     }
     best = block_max_f64(best, lds);
     if (threadIdx.x == 0)
@@ -426,7 +604,7 @@ k_atr_absmax(const char *__restrict__ seg, const int64_t *__restrict__ pc, const
 }
 
 // --------------------------------------------------------------------------
-// Set-up: validation and packing into the segment layout.
+// Set-up: validation and packing into the record layout.
 // --------------------------------------------------------------------------
 
 // dpad[i] = nonzeros of column i rounded up to 4 (dpad[n] = 0); flags bad pointers.
@@ -455,26 +633,38 @@ k_check_ptr(const int64_t *__restrict__ col_ptr, int64_t n, int64_t nnz, int64_t
     }
 }
 
+// Flags columns whose padded length differs from column 0's.
+__global__ void __launch_bounds__(kBlock)
+k_check_uniform(const int64_t *__restrict__ dpad, int64_t n, Ctrl *__restrict__ ctrl)
+{
+    const int64_t d0 = dpad[0];
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        if (dpad[i] != d0)
+            ctrl->nonuniform = 1u;
+}
+
 __device__ __forceinline__ bool finite_val(float v) { return isfinite(v); }
 __device__ __forceinline__ bool finite_val(double v) { return isfinite(v); }
 __device__ __forceinline__ bool finite_val(bf16s v) { return ((v.bits >> 7) & 0xFF) != 0xFF; }
 
-// Copy column i into its segment; L_i in float64 -> invL; row histogram of nonzeros.
+// Copy column i into its record (x_i = 0, 1/L_i from float64 sums of the
+// stored values); row histogram of the nonzeros (for omega).
 template <typename V>
 __global__ void __launch_bounds__(kBlock)
 k_pack(const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ row_idx, const V *__restrict__ val,
-       const int64_t *__restrict__ pc, int64_t n, int64_t m, char *__restrict__ seg,
-       typename ValT<V>::T *__restrict__ invL, int32_t *__restrict__ hist, Ctrl *__restrict__ ctrl)
+       Layout lay, int64_t n, int64_t m, char *__restrict__ seg, int32_t *__restrict__ hist,
+       Ctrl *__restrict__ ctrl)
 {
-    using T = typename ValT<V>::T;
-    constexpr int EB = entry_bytes<V>();
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         const int64_t a = col_ptr[i], b = col_ptr[i + 1];
-        const int64_t p0 = pc[i], dpad = pc[i + 1] - p0;
-        int32_t *rows = reinterpret_cast<int32_t *>(seg + p0 * EB);
-        V *vals = reinterpret_cast<V *>(seg + p0 * EB + 4 * dpad);
+        int64_t off;
+        int32_t dpad;
+        locate<V>(lay, i, off, dpad);
         if (b <= a || dpad < b - a)
             continue;  // flagged by k_check_ptr
+        double *hdr = reinterpret_cast<double *>(seg + off);
+        int32_t *rows = reinterpret_cast<int32_t *>(seg + off + kHeader);
+        V *vals = reinterpret_cast<V *>(seg + off + kHeader + 4 * (int64_t)dpad);
         uint32_t err = 0;
         double L = 0.0;
         bool sorted = true;
@@ -511,12 +701,16 @@ k_pack(const int64_t *__restrict__ col_ptr, const int32_t *__restrict__ row_idx,
         for (int64_t p = b - a; p < dpad; ++p) {
             rows[p] = last;
             V z;
-            if constexpr (sizeof(V) == 2) z.bits = 0; else z = V(0);
+            if constexpr (sizeof(V) == 2)
+                z.bits = 0;
+            else
+                z = V(0);
             vals[p] = z;
         }
         if (!(L > 0.0))
             err |= ERR_ZEROCOL;
-        invL[i] = (T)(L > 0.0 ? 1.0 / L : 0.0);
+        hdr[0] = 0.0;
+        hdr[1] = L > 0.0 ? 1.0 / L : 0.0;
         if (err)
             atomicOr(&ctrl->err, err);
     }
@@ -558,7 +752,7 @@ k_imax_final(const int64_t *__restrict__ part, int nparts, Ctrl *__restrict__ ct
         ctrl->imax = lds[0];
 }
 
-// Per-slot sum of nz_part (counter of nonzero updates).
+// Sum of the per-block counters of nonzero updates.
 __global__ void __launch_bounds__(kBlock)
 k_sum_u64(const uint64_t *__restrict__ part, int nparts, Ctrl *__restrict__ ctrl)
 {
@@ -566,7 +760,7 @@ k_sum_u64(const uint64_t *__restrict__ part, int nparts, Ctrl *__restrict__ ctrl
     uint64_t s = 0;
     for (int q = threadIdx.x; q < nparts; q += kBlock)
         s += part[q];
-    s = block_sum_u64<double>(s, lds);
+    s = block_sum_u64(s, lds);
     if (threadIdx.x == 0)
         ctrl->imax = (int64_t)s;
 }

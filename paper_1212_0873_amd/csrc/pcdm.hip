@@ -14,6 +14,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 #include "pcdm.h"
@@ -70,6 +71,15 @@ int grid_for(int64_t items, int64_t per_block, int cap)
 
 constexpr int kReduceBlocks = 1024;
 
+// Device time of one kernel kind, from HIP events recorded around each launch.
+struct KernelClock {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+enum { CLK_GATHER = 0, CLK_SCATTER = 1, CLK_REFRESH = 2, CLK_COUNT = 3 };
+
 }  // namespace
 
 struct pcdm_problem {
@@ -83,14 +93,17 @@ struct pcdm_problem {
     uint64_t seed = 0;
     int64_t k_host = 0;
     int64_t refresh_every = 0;
-    int lanes = 4;
+    int lanes = 8;
+    int chunks = 1;
     int lanes_auto = 1;
     int nblk_max = 2048;
     hipStream_t last_stream = nullptr;
 
     char *seg = nullptr;
     int64_t *pc = nullptr;
-    void *invL = nullptr, *x = nullptr, *r = nullptr;
+    Layout lay{nullptr, 0, 0};
+    double *x = nullptr;  // dense mirror of the x_i in the column records
+    void *r = nullptr;
     double *r64 = nullptr, *b64 = nullptr;
     int32_t *id_slot = nullptr;
     void *delta_slot = nullptr;
@@ -99,6 +112,10 @@ struct pcdm_problem {
     uint64_t *nz_part = nullptr;
     double *part = nullptr;   // kReduceBlocks * 3
     double *part2 = nullptr;  // nblk_max
+
+    int timing = 0;
+    KernelClock clocks[CLK_COUNT];
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -107,7 +124,14 @@ void free_problem(pcdm_problem *P)
 {
     if (!P)
         return;
-    void *bufs[] = {P->seg, P->pc, P->invL, P->x, P->r, P->r64, P->b64, P->id_slot,
+    for (auto &c : P->clocks)
+        for (auto &pr : c.pending) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : P->event_pool)
+        (void)hipEventDestroy(e);
+    void *bufs[] = {P->seg, P->pc, P->x, P->r, P->r64, P->b64, P->id_slot,
                     P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2};
     for (void *b : bufs)
         if (b)
@@ -125,14 +149,90 @@ int compute_beta(pcdm_problem *P)
     return PCDM_OK;
 }
 
-int pick_lanes(const pcdm_problem *P)
+// Tile schedule from the mean padded column length: G lanes per column with
+// C chunks (of 4 entries) each, G*C >= the mean number of chunks.
+void pick_schedule(pcdm_problem *P)
 {
-    // chunks of 4 entries per column; aim at about two chunks per lane
     const double chunks = (double)P->stored_nnz / (4.0 * (double)P->n);
-    int g = 1;
-    while (g < 64 && 2.0 * g < chunks)
-        g *= 2;
-    return g;
+    if (chunks <= 1.0) {
+        P->lanes = 1; P->chunks = 1;
+    } else if (chunks <= 2.0) {
+        P->lanes = 2; P->chunks = 1;
+    } else if (chunks <= 4.0) {
+        P->lanes = 4; P->chunks = 1;
+    } else if (chunks <= 8.0) {
+        P->lanes = 8; P->chunks = 1;
+    } else if (chunks <= 16.0) {
+        P->lanes = 16; P->chunks = 1;
+    } else if (chunks <= 32.0) {
+        P->lanes = 32; P->chunks = 1;
+    } else {
+        P->lanes = 64; P->chunks = 1;
+    }
+}
+
+bool schedule_supported(int g, int c)
+{
+    switch (g * 16 + c) {
+    case 1 * 16 + 1: case 1 * 16 + 2: case 1 * 16 + 4: case 2 * 16 + 1: case 2 * 16 + 2:
+    case 2 * 16 + 4: case 4 * 16 + 1: case 4 * 16 + 2: case 8 * 16 + 1: case 8 * 16 + 2:
+    case 16 * 16 + 1: case 32 * 16 + 1: case 64 * 16 + 1:
+        return true;
+    default:
+        return false;
+    }
+}
+
+hipEvent_t take_event(pcdm_problem *P)
+{
+    hipEvent_t e = nullptr;
+    if (!P->event_pool.empty()) {
+        e = P->event_pool.back();
+        P->event_pool.pop_back();
+        return e;
+    }
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Record a start event for a kernel kind (no-op unless timing is on).
+hipEvent_t clock_start(pcdm_problem *P, hipStream_t s)
+{
+    if (!P->timing)
+        return nullptr;
+    hipEvent_t e = take_event(P);
+    if (e)
+        (void)hipEventRecord(e, s);
+    return e;
+}
+
+void clock_stop(pcdm_problem *P, int kind, hipEvent_t start, hipStream_t s)
+{
+    if (!P->timing || !start)
+        return;
+    hipEvent_t e = take_event(P);
+    if (!e)
+        return;
+    (void)hipEventRecord(e, s);
+    P->clocks[kind].pending.emplace_back(start, e);
+}
+
+// Fold finished event pairs into the totals (synchronises on the events).
+int clock_collect(pcdm_problem *P, int kind)
+{
+    KernelClock &c = P->clocks[kind];
+    for (auto &pr : c.pending) {
+        HIP_TRY(hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        c.total_ms += ms;
+        c.launches += 1;
+        P->event_pool.push_back(pr.first);
+        P->event_pool.push_back(pr.second);
+    }
+    c.pending.clear();
+    return PCDM_OK;
 }
 
 int ensure_slots(pcdm_problem *P, int64_t tau)
@@ -159,30 +259,38 @@ int ensure_slots(pcdm_problem *P, int64_t tau)
 template <typename V> struct Ops {
     using T = typename ValT<V>::T;
 
-    template <int G> static void launch_step(pcdm_problem *P, hipStream_t s)
+    template <int G, int C> static void launch_step(pcdm_problem *P, hipStream_t s)
     {
-        const int gpb = kBlock / G;
-        const int grid = grid_for(P->tau, gpb, P->nblk_max);
-        hipLaunchKernelGGL((k_gather<V, G>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->pc,
-                           (const T *)P->r, (T *)P->x, (const T *)P->invL, P->id_slot,
-                           (T *)P->delta_slot, P->ctrl, P->nz_part, P->seed, P->tau,
-                           (uint32_t)P->n, (T)(1.0 / P->beta), (T)P->lambda);
-        hipLaunchKernelGGL((k_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->pc,
+        const int grid = grid_for(P->tau, kBlock, P->nblk_max);  // one slot per thread per tile
+        hipEvent_t t0 = clock_start(P, s);
+        hipLaunchKernelGGL((k_gather<V, G, C>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
+                           (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part,
+                           P->seed, P->tau, (uint32_t)P->n, 1.0 / P->beta, P->lambda);
+        clock_stop(P, CLK_GATHER, t0, s);
+        hipEvent_t t1 = clock_start(P, s);
+        hipLaunchKernelGGL((k_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
                            (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl,
                            P->tau);
+        clock_stop(P, CLK_SCATTER, t1, s);
     }
 
     static int step_once(pcdm_problem *P, hipStream_t s)
     {
-        switch (P->lanes) {
-        case 1: launch_step<1>(P, s); break;
-        case 2: launch_step<2>(P, s); break;
-        case 4: launch_step<4>(P, s); break;
-        case 8: launch_step<8>(P, s); break;
-        case 16: launch_step<16>(P, s); break;
-        case 32: launch_step<32>(P, s); break;
-        case 64: launch_step<64>(P, s); break;
-        default: return fail(PCDM_EINVAL, "lanes_per_column must be a power of two <= 64");
+        switch (P->lanes * 16 + P->chunks) {
+        case 1 * 16 + 1: launch_step<1, 1>(P, s); break;
+        case 1 * 16 + 2: launch_step<1, 2>(P, s); break;
+        case 1 * 16 + 4: launch_step<1, 4>(P, s); break;
+        case 2 * 16 + 1: launch_step<2, 1>(P, s); break;
+        case 2 * 16 + 2: launch_step<2, 2>(P, s); break;
+        case 2 * 16 + 4: launch_step<2, 4>(P, s); break;
+        case 4 * 16 + 1: launch_step<4, 1>(P, s); break;
+        case 4 * 16 + 2: launch_step<4, 2>(P, s); break;
+        case 8 * 16 + 1: launch_step<8, 1>(P, s); break;
+        case 8 * 16 + 2: launch_step<8, 2>(P, s); break;
+        case 16 * 16 + 1: launch_step<16, 1>(P, s); break;
+        case 32 * 16 + 1: launch_step<32, 1>(P, s); break;
+        case 64 * 16 + 1: launch_step<64, 1>(P, s); break;
+        default: return fail(PCDM_EINVAL, "unsupported (lanes_per_column, chunks_per_lane) pair");
         }
         return PCDM_OK;
     }
@@ -193,8 +301,8 @@ template <typename V> struct Ops {
         const int gm = grid_for(P->m, kBlock, P->nblk_max);
         const int gn = grid_for(P->n, kBlock, P->nblk_max);
         hipLaunchKernelGGL(k_neg_copy, dim3(gm), dim3(kBlock), 0, s, (const double *)P->b64, P->r64, P->m);
-        hipLaunchKernelGGL((k_refresh_cols<V>), dim3(gn), dim3(kBlock), 0, s, P->seg, P->pc,
-                           (const T *)P->x, P->r64, P->n);
+        hipLaunchKernelGGL((k_refresh_cols<V, 8>), dim3(gn), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                           (const double *)P->x, P->r64, P->n);
     }
 
     static void refresh(pcdm_problem *P, hipStream_t s)
@@ -204,46 +312,40 @@ template <typename V> struct Ops {
         hipLaunchKernelGGL((k_narrow<T>), dim3(gm), dim3(kBlock), 0, s, (const double *)P->r64, (T *)P->r, P->m);
     }
 
-    template <int G> static void launch_atr(pcdm_problem *P, const double *rv, hipStream_t s)
-    {
-        const int grid = grid_for(P->n, kBlock / G, P->nblk_max);
-        hipLaunchKernelGGL((k_atr_absmax<V, G>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->pc, rv, P->n,
-                           P->part2);
-        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
-                           P->ctrl->scal + 3);
-    }
-
     // ctrl->scal[3] = max_i |a_i^T rv|
     static int atr_absmax(pcdm_problem *P, const double *rv, hipStream_t s)
     {
-        switch (P->lanes) {
-        case 1: launch_atr<1>(P, rv, s); break;
-        case 2: launch_atr<2>(P, rv, s); break;
-        case 4: launch_atr<4>(P, rv, s); break;
-        case 8: launch_atr<8>(P, rv, s); break;
-        case 16: launch_atr<16>(P, rv, s); break;
-        case 32: launch_atr<32>(P, rv, s); break;
-        default: launch_atr<64>(P, rv, s); break;
-        }
+        const int grid = grid_for(P->n, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_atr_absmax<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                           rv, P->n, P->part2);
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
+                           P->ctrl->scal + 3);
         return PCDM_OK;
     }
 
     // ctrl->scal[0..2] = ||r64||^2, b.r64, ||x||_1
     static void sums(pcdm_problem *P, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_obj_partials<T>), dim3(kReduceBlocks), dim3(kBlock), 0, s,
-                           (const double *)P->r64, (const double *)P->b64, (const T *)P->x, P->m, P->n,
+        hipLaunchKernelGGL(k_obj_partials, dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                           (const double *)P->r64, (const double *)P->b64, (const double *)P->x, P->m, P->n,
                            P->part);
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part, kReduceBlocks, 3, 0,
                            P->ctrl->scal);
+    }
+
+    static void x_to_records(pcdm_problem *P, hipStream_t s)
+    {
+        const int g = grid_for(P->n, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_x_to_records<V>), dim3(g), dim3(kBlock), 0, s, P->seg, P->lay, (const double *)P->x,
+                           P->n);
     }
 
     static int pack(pcdm_problem *P, const int64_t *col_ptr, const int32_t *rows, const void *vals,
                     int32_t *hist, hipStream_t s)
     {
         const int gn = grid_for(P->n, kBlock, P->nblk_max);
-        hipLaunchKernelGGL((k_pack<V>), dim3(gn), dim3(kBlock), 0, s, col_ptr, rows, (const V *)vals,
-                           (const int64_t *)P->pc, P->n, P->m, P->seg, (T *)P->invL, hist, P->ctrl);
+        hipLaunchKernelGGL((k_pack<V>), dim3(gn), dim3(kBlock), 0, s, col_ptr, rows, (const V *)vals, P->lay,
+                           P->n, P->m, P->seg, hist, P->ctrl);
         return PCDM_OK;
     }
 };
@@ -268,10 +370,12 @@ int check_launch(const char *what)
 
 int refresh_now(pcdm_problem *P, hipStream_t s)
 {
+    hipEvent_t t0 = clock_start(P, s);
     dispatch(P->dtype, [&](auto ops) {
         decltype(ops)::refresh(P, s);
         return PCDM_OK;
     });
+    clock_stop(P, CLK_REFRESH, t0, s);
     return check_launch("refresh");
 }
 
@@ -305,6 +409,8 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
         return fail(PCDM_EINVAL, "unknown dtype");
     if (tau < 1 || tau > A->n)
         return fail(PCDM_EINVAL, "need 1 <= tau <= n");
+    if ((uint64_t)A->m * (A->dtype == PCDM_F64 ? 8u : 4u) >= (1ull << 32))
+        return fail(PCDM_EINVAL, "the residual must span < 4 GiB (m < 2^30 for float32/bf16, m < 2^29 for float64)");
     if (!(lambda >= 0.0) || !std::isfinite(lambda))
         return fail(PCDM_EINVAL, "lambda must be finite and >= 0");
 
@@ -383,15 +489,22 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
         HIP_TRY(hipMalloc(&guard.tmp[5], std::max<size_t>(tmp_bytes, 16)));
         HIP_TRY(hipcub::DeviceScan::ExclusiveSum(guard.tmp[5], tmp_bytes, dpad, P->pc, (int)(A->n + 1), s));
         HIP_TRY(hipMemcpy(&P->stored_nnz, P->pc + A->n, 8, hipMemcpyDeviceToHost));
+        hipLaunchKernelGGL(k_check_uniform, dim3(g), dim3(kBlock), 0, s, (const int64_t *)dpad, A->n, P->ctrl);
+        PCDM_TRY(check_launch("k_check_uniform"));
+        HIP_TRY(hipMemcpy(&hc, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        P->lay.pc = P->pc;
+        if (!hc.nonuniform) {
+            HIP_TRY(hipMemcpy(&P->lay.fixed_dpad, dpad, 8, hipMemcpyDeviceToHost));
+            P->lay.stride = kHeader + P->lay.fixed_dpad * (int64_t)(4 + vb);
+        }
     }
 
-    HIP_TRY(hipMalloc(&P->seg, (size_t)P->stored_nnz * (4 + vb)));
-    HIP_TRY(hipMalloc(&P->invL, (size_t)A->n * P->tbytes));
-    HIP_TRY(hipMalloc(&P->x, (size_t)A->n * P->tbytes));
+    HIP_TRY(hipMalloc(&P->seg, (size_t)P->stored_nnz * (4 + vb) + (size_t)kHeader * A->n));
+    HIP_TRY(hipMalloc(&P->x, (size_t)A->n * 8));
     HIP_TRY(hipMalloc(&P->r, (size_t)A->m * P->tbytes));
     HIP_TRY(hipMalloc(&P->r64, (size_t)A->m * 8));
     HIP_TRY(hipMalloc(&P->b64, (size_t)A->m * 8));
-    HIP_TRY(hipMemset(P->x, 0, (size_t)A->n * P->tbytes));
+    HIP_TRY(hipMemset(P->x, 0, (size_t)A->n * 8));
     HIP_TRY(hipMemcpy(P->b64, bdev, (size_t)A->m * 8, hipMemcpyDeviceToDevice));
     PCDM_TRY(ensure_slots(P, tau));
 
@@ -422,7 +535,7 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
         P->omega = hc.imax;
     }
 
-    P->lanes = pick_lanes(P);
+    pick_schedule(P);
     P->lanes_auto = 1;
     compute_beta(P);
     P->refresh_every = ceil_div(P->n, P->tau);
@@ -510,17 +623,29 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         PCDM_TRY(ensure_slots(h, t));
         h->tau = t;
         compute_beta(h);
-    } else if (k == "lanes_per_column") {
-        const int g = (int)value;
-        if (g == 0) {
-            h->lanes = pick_lanes(h);
+    } else if (k == "lanes_per_column" || k == "chunks_per_lane") {
+        const int v = (int)value;
+        if ((double)v != value || v < 0)
+            return fail(PCDM_EINVAL, k + " must be a non-negative integer");
+        if (v == 0) {
+            pick_schedule(h);
             h->lanes_auto = 1;
-        } else if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) {
-            h->lanes = g;
-            h->lanes_auto = 0;
         } else {
-            return fail(PCDM_EINVAL, "lanes_per_column must be 0 or a power of two <= 64");
+            const int g = k == "lanes_per_column" ? v : h->lanes;
+            const int c = k == "chunks_per_lane" ? v : (schedule_supported(v, h->chunks) ? h->chunks : 1);
+            if (!schedule_supported(g, c))
+                return fail(PCDM_EINVAL, "unsupported (lanes_per_column, chunks_per_lane) pair");
+            h->lanes = g;
+            h->chunks = c;
+            h->lanes_auto = 0;
         }
+    } else if (k == "kernel_timing") {
+        for (int c = 0; c < CLK_COUNT; ++c) {
+            PCDM_TRY(clock_collect(h, c));
+            h->clocks[c].launches = 0;
+            h->clocks[c].total_ms = 0.0;
+        }
+        h->timing = value != 0.0;
     } else if (k == "reset_counters") {
         hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(kBlock), 0, h->last_stream, h->nz_part,
                            (uint64_t)0, (int64_t)h->nblk_max);
@@ -557,6 +682,7 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->dtype = h->dtype;
     out->beta_rule = h->beta_rule;
     out->lanes_per_column = h->lanes;
+    out->chunks_per_lane = h->chunks;
     return PCDM_OK;
 }
 
@@ -620,17 +746,10 @@ int pcdm_get_x(pcdm_problem *h, void *x_out, int32_t dtype, int32_t on_device, v
     if (tmp)
         dst = tmp;
     const int g = grid_for(h->n, kBlock, h->nblk_max);
-    if (h->dtype == PCDM_F64) {
-        if (dtype == PCDM_F64)
-            hipLaunchKernelGGL((k_convert<double, double>), dim3(g), dim3(kBlock), 0, s, (const double *)h->x, (double *)dst, h->n);
-        else
-            hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(kBlock), 0, s, (const double *)h->x, (float *)dst, h->n);
-    } else {
-        if (dtype == PCDM_F64)
-            hipLaunchKernelGGL((k_convert<float, double>), dim3(g), dim3(kBlock), 0, s, (const float *)h->x, (double *)dst, h->n);
-        else
-            hipLaunchKernelGGL((k_convert<float, float>), dim3(g), dim3(kBlock), 0, s, (const float *)h->x, (float *)dst, h->n);
-    }
+    if (dtype == PCDM_F64)
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(g), dim3(kBlock), 0, s, (const double *)h->x, (double *)dst, h->n);
+    else
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(kBlock), 0, s, (const double *)h->x, (float *)dst, h->n);
     int st = check_launch("pcdm_get_x");
     if (tmp) {
         if (st == PCDM_OK) {
@@ -668,18 +787,15 @@ int pcdm_set_x(pcdm_problem *h, const void *x, int32_t dtype, int32_t on_device,
         src = tmp;
     }
     const int g = grid_for(h->n, kBlock, h->nblk_max);
-    if (h->dtype == PCDM_F64) {
-        if (dtype == PCDM_F64)
-            hipLaunchKernelGGL((k_convert<double, double>), dim3(g), dim3(kBlock), 0, s, (const double *)src, (double *)h->x, h->n);
-        else
-            hipLaunchKernelGGL((k_convert<float, double>), dim3(g), dim3(kBlock), 0, s, (const float *)src, (double *)h->x, h->n);
-    } else {
-        if (dtype == PCDM_F64)
-            hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(kBlock), 0, s, (const double *)src, (float *)h->x, h->n);
-        else
-            hipLaunchKernelGGL((k_convert<float, float>), dim3(g), dim3(kBlock), 0, s, (const float *)src, (float *)h->x, h->n);
-    }
-    hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(64), 0, s, &h->ctrl->k, (uint64_t)k, (int64_t)1);
+    if (dtype == PCDM_F64)
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(g), dim3(kBlock), 0, s, (const double *)src, (double *)h->x, h->n);
+    else
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(g), dim3(kBlock), 0, s, (const float *)src, (double *)h->x, h->n);
+    dispatch(h->dtype, [&](auto ops) {
+        decltype(ops)::x_to_records(h, s);
+        return PCDM_OK;
+    });
+    hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(kBlock), 0, s, &h->ctrl->k, (uint64_t)k, (int64_t)1);
     int st = check_launch("pcdm_set_x");
     if (st == PCDM_OK)
         st = refresh_now(h, s);
@@ -735,6 +851,20 @@ int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db, doub
     if (!h)
         return fail(PCDM_EINVAL, "NULL handle");
     return fail(PCDM_ESTATE, "pcdm_grad_backward: not available in this build");
+}
+
+int pcdm_kernel_time(pcdm_problem *h, const char *kernel, int64_t *launches, double *total_ms)
+{
+    if (!h || !kernel || !launches || !total_ms)
+        return fail(PCDM_EINVAL, "NULL argument");
+    const std::string k(kernel);
+    int kind = k == "gather" ? CLK_GATHER : k == "scatter" ? CLK_SCATTER : k == "refresh" ? CLK_REFRESH : -1;
+    if (kind < 0)
+        return fail(PCDM_EINVAL, "kernel must be \"gather\", \"scatter\" or \"refresh\"");
+    PCDM_TRY(clock_collect(h, kind));
+    *launches = h->clocks[kind].launches;
+    *total_ms = h->clocks[kind].total_ms;
+    return PCDM_OK;
 }
 
 int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device, void *stream)
