@@ -29,11 +29,11 @@ sys.path.insert(0, ROOT)
 METRIC = "coord updates/s + HBM GB/s (% roofline); time to 1e-6 rel. objective gap"
 HBM_PEAK_GBPS = 8000.0
 WORKLOAD_NAMES = {
-    "c1": "lasso_2000x1000_d20_uniform",
-    "c2": "lasso_1e6x1e7_d20_balanced",
-    "c2b": "lasso_3.33e6x1e7_d20_balanced",
-    "c4": "lasso_1e5x1e6_d10_uniform",
-    "c5": "lasso_2e8x5e8_d20_balanced",
+    "small_2000x1000": "lasso_2000x1000_d20_uniform",
+    "lasso_1e6x1e7": "lasso_1e6x1e7_d20_balanced",
+    "lasso_3.33e6x1e7": "lasso_3.33e6x1e7_d20_balanced",
+    "train_1e5x1e6": "lasso_1e5x1e6_d10_uniform",
+    "lasso_2e8x5e8": "lasso_2e8x5e8_d20_balanced",
 }
 KERNEL_SOURCES = ("kernels.hpp", "sampler.hpp", "pcdm.hip")
 
@@ -49,7 +49,7 @@ def kernel_source_hash() -> str:
 def read_traffic(kernel: str, workload: str, dtype: str, tau: int):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{dtype}_tau{tau}.txt")
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{WORKLOAD_NAMES[workload]}_{dtype}_tau{tau}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -79,9 +79,9 @@ def algorithmic_bytes(d_avg: float, s_val: int):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOAD_NAMES))
+    ap.add_argument("--config", default="lasso_1e6x1e7", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--tau", type=int, default=1_000_000)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--lanes", type=int, default=0, help="lanes per column (0 = automatic)")

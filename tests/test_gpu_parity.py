@@ -81,8 +81,8 @@ def _compare_run(pc, A, b, lam, tau, seed, epochs, log_every, rtol_F, x_atol=Non
 
 @pytest.mark.parametrize("tau", [1, 8])
 def test_small_config_float64_matches_oracle(pc, tau):
-    inst = make_config("c1", dtype="f64")
-    _say(f"c1 f64 tau={tau}")
+    inst = make_config("small_2000x1000", dtype="f64")
+    _say(f"small f64 tau={tau}")
     worst, ref, info = _compare_run(pc, inst.A, inst.b, inst.lam, tau, 0, 200, 20, 1e-10, x_atol=1e-9)
     _say(f"  worst rel F diff {worst:.2e}, oracle changed {ref.changed}, gpu nonzero {info['nonzero_updates']}")
     # The count of nonzero updates is reported, not compared: near convergence
@@ -92,15 +92,15 @@ def test_small_config_float64_matches_oracle(pc, tau):
 
 @pytest.mark.parametrize("tau", [1, 8])
 def test_small_config_float32_matches_oracle(pc, tau):
-    inst = make_config("c1", dtype="f32")
-    _say(f"c1 f32 tau={tau}")
+    inst = make_config("small_2000x1000", dtype="f32")
+    _say(f"small f32 tau={tau}")
     worst, _, _ = _compare_run(pc, inst.A, inst.b, inst.lam, tau, 0, 200, 10, 1e-5)
     _say(f"  worst rel F diff {worst:.2e}")
 
 
 def test_small_config_bf16_matches_oracle(pc):
-    inst = make_config("c1", dtype="bf16")
-    _say("c1 bf16 tau=8")
+    inst = make_config("small_2000x1000", dtype="bf16")
+    _say("small bf16 tau=8")
     worst, _, _ = _compare_run(pc, inst.A, inst.b, inst.lam, 8, 0, 200, 10, 1e-5)
     _say(f"  worst rel F diff {worst:.2e}")
 
@@ -197,7 +197,7 @@ def test_orthonormal_columns_converge_to_closed_form(pc, dtype, tol):
 def test_residual_invariant_float32(pc):
     """Stored r vs A x - b computed independently (scipy): drift within an
     epoch is small, and the float64 refresh at the epoch end removes it."""
-    inst = make_config("c2", scale=0.01, dtype="f32", tau=1000)
+    inst = make_config("lasso_1e6x1e7", scale=0.01, dtype="f32", tau=1000)
     S = _sparse(inst.A)
     with pc.Problem(inst.A, inst.b, inst.lam, 1000, seed=1) as p:
         spe = p.info()["refresh_every"]
@@ -250,7 +250,7 @@ def test_objective_and_gap_at_given_point_match_oracle(pc):
 
 
 def test_set_x_resumes_the_same_trajectory(pc):
-    inst = make_config("c1", dtype="f64")
+    inst = make_config("small_2000x1000", dtype="f64")
     with pc.Problem(inst.A, inst.b, inst.lam, 8, seed=3) as p:
         p.step(300)
         x_mid = p.get_x()
@@ -325,7 +325,7 @@ def test_valid_tiny_matrix_accepted(pc):
 @pytest.fixture(scope="module")
 def c2_full():
     _say("generating 1e6 x 1e7 instance (2e8 nnz)")
-    return make_config("c2", dtype="f32", tau=1_000_000)
+    return make_config("lasso_1e6x1e7", dtype="f32", tau=1_000_000)
 
 
 def test_full_size_steps_match_oracle(pc, c2_full):

@@ -21,21 +21,21 @@ from .lasso import LassoInstance, planted_lasso, random_csc
 # name -> recipe (all sizes at full scale; ``scale`` shrinks n and m together)
 CONFIGS: Dict[str, dict] = {
     # small FP64 parity case: 2000 x 1000, 20 nnz/col uniform rows, unit columns
-    "c1": dict(m=2000, n=1000, d=20, balanced=False, normalize=True, xstar_nnz=50,
+    "small_2000x1000": dict(m=2000, n=1000, d=20, balanced=False, normalize=True, xstar_nnz=50,
                noise_std=0.01, lam_factor=0.1, taus=(1, 8), epochs=200),
     # paper-shaped single instance: 1e6 x 1e7, 20 nnz/col from balanced slots
-    "c2": dict(m=1_000_000, n=10_000_000, d=20, balanced=True, normalize=True,
+    "lasso_1e6x1e7": dict(m=1_000_000, n=10_000_000, d=20, balanced=True, normalize=True,
                xstar_nnz=10_000, noise_std=1e-2, lam_factor=0.05,
                taus=(1024, 65536, 1_000_000)),
     # same with more rows so that the balanced maximum row degree is ~60
-    "c2b": dict(m=3_330_000, n=10_000_000, d=20, balanced=True, normalize=True,
+    "lasso_3.33e6x1e7": dict(m=3_330_000, n=10_000_000, d=20, balanced=True, normalize=True,
                 xstar_nnz=10_000, noise_std=1e-2, lam_factor=0.05,
                 taus=(1024, 65536, 1_000_000)),
     # differentiable LASSO (train part): 1e5 x 1e6, 10 nnz/col, N(0,1) values
-    "c4": dict(m=100_000, n=1_000_000, d=10, balanced=False, normalize=False,
+    "train_1e5x1e6": dict(m=100_000, n=1_000_000, d=10, balanced=False, normalize=False,
                xstar_nnz=2000, noise_std=0.1, lam_factor=0.1, taus=(4096,)),
     # big single-GPU instance: 2e8 x 5e8, 20 nnz/col, balanced slots
-    "c5": dict(m=200_000_000, n=500_000_000, d=20, balanced=True, normalize=True,
+    "lasso_2e8x5e8": dict(m=200_000_000, n=500_000_000, d=20, balanced=True, normalize=True,
                xstar_nnz=100_000, noise_std=1e-2, lam_factor=0.05,
                taus=(65536, 1 << 20)),
 }
