@@ -137,6 +137,8 @@ const char *pcdm_last_error(void);
  *                      column each lane keeps in registers; supported pairs
  *                      (lanes, chunks): (1|2, 1|2|4), (4|8, 1|2), (16|32|64, 1);
  *   "reset_counters"   any value: zero nonzero_updates;
+ *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
+ *                      settings of pcdm_grad_backward's solve (see there);
  *   "kernel_timing"    1 = record HIP events around every step-kernel launch
  *                      (see pcdm_kernel_time), 0 = stop; either value first
  *                      zeroes the accumulated times.
@@ -180,15 +182,30 @@ int pcdm_get_residual(pcdm_problem *h, double *r_out, int32_t on_device, void *s
  * solution: with S = {i : x_i != 0}, s = sign(x_S) and A_S^T A_S x_S =
  * A_S^T b - lambda s on a stable support,
  *     dL/db = A_S v,   dL/dlambda = -s^T v,   where A_S^T A_S v = (dL/dx)_S.
- * v is found by PCDM steps (lambda = 0, same kernels) on
- * q(v) = 0.5||A_S v||^2 - g^T v until ||A_S^T A_S v - g||_inf <= tol * ||g||_inf
- * (option values at create: tol 1e-6, at most 20000 epochs).
+ * (the derivative of the solution map on a stable support: differentiating
+ * the optimality conditions of the LASSO).  v is found by synchronous PCDM
+ * steps with the same tau-nice sampler and column reads as pcdm_step, in
+ * float64, on q(v) = 0.5||A_S v||^2 - g^T v (lambda = 0, coordinates = S,
+ * beta from omega_S of the columns in S and tau_S = min(adj_tau or tau, |S|),
+ * sampler key seed ^ 0xAD101E5EED), until
+ * ||A_S^T A_S v - g_S||_inf <= adj_tol * ||g_S||_inf, checked every
+ * adj_check_every epochs (options; defaults 1e-6, 10, at most adj_max_epochs
+ * = 20000 epochs).
  *   dL_dx [n] float64, dL_db [m] float64 (out), dL_dlambda (out, host scalar);
- * dL_dx and dL_db are host or device as on_device says.  Synchronous.
- * PCDM_ENOTCONV if the tolerance is not met (outputs still written).
+ * dL_dx and dL_db are host or device as on_device says.  x_i == 0 exactly
+ * defines the inactive set.  Synchronous.  PCDM_ENOTCONV if the tolerance is
+ * not met (outputs still written).  Temporary device memory: about
+ * 17 n + 12 m + 12 tau bytes, freed before return.
  */
 int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db,
                        double *dL_dlambda, int32_t on_device, void *stream);
+
+/*
+ * Replace b (m float64 values, host or device) and recompute r = A x - b in
+ * float64 and ||A^T b||_inf (pcdm_info.atb_inf).  x and k are kept (warm
+ * start).  Synchronous.
+ */
+int pcdm_set_rhs(pcdm_problem *h, const double *b, int32_t on_device, void *stream);
 
 /*
  * Device time of one kernel kind of the step while option "kernel_timing" is

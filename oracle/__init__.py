@@ -236,3 +236,32 @@ class Solver:
 
     def steps_per_epoch(self) -> int:
         return -(-self.n // self.tau)
+
+
+# --------------------------------------------------------------------------- #
+# adjoint through the LASSO solution (float64 support solve)
+# --------------------------------------------------------------------------- #
+
+def lasso_adjoint(A, x, g):
+    """(dL/db, dL/dlambda) for L(x(b, lambda)) at a LASSO solution x.
+
+    On the support S of x with signs s the optimality conditions read
+    A_S^T (A_S x_S - b) + lambda s = 0, so x_S = (A_S^T A_S)^{-1}(A_S^T b - lambda s)
+    while S and s stay fixed.  With v = (A_S^T A_S)^{-1} g_S (g = dL/dx):
+    dL/db = A_S v and dL/dlambda = -s^T v.  The normal matrix is formed in
+    float64 and solved directly (library Cholesky / LU)."""
+    import scipy.linalg
+    import scipy.sparse as sp
+    x = np.asarray(x, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    S = np.nonzero(x)[0]
+    if S.size == 0:
+        return np.zeros(A.m), 0.0
+    M = sp.csc_matrix((A.values_f64(), A.row_idx, A.col_ptr), shape=(A.m, A.n))[:, S]
+    G = (M.T @ M).toarray()
+    try:
+        v = scipy.linalg.cho_solve(scipy.linalg.cho_factor(G), g[S])
+    except np.linalg.LinAlgError:
+        v = np.linalg.lstsq(G, g[S], rcond=None)[0]
+    s = np.sign(x[S])
+    return np.asarray(M @ v).ravel(), float(-(s @ v))

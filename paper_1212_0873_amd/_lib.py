@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "PCDM_OK", -1: "PCDM_EINVAL", -2: "PCDM_ENOMEM", -3: "PCDM_ED
 # every symbol include/pcdm.h declares
 EXPORTS = ("pcdm_create", "pcdm_destroy", "pcdm_last_error", "pcdm_set_option", "pcdm_get_info",
            "pcdm_step", "pcdm_objective", "pcdm_get_x", "pcdm_set_x", "pcdm_get_residual",
-           "pcdm_grad_backward", "pcdm_kernel_time", "pcdm_sample")
+           "pcdm_grad_backward", "pcdm_set_rhs", "pcdm_kernel_time", "pcdm_sample")
 
 
 class pcdm_csc(ctypes.Structure):
@@ -70,6 +70,7 @@ def load() -> ctypes.CDLL:
             "pcdm_grad_backward": [vp, vp, vp, pd, i32, vp],
             "pcdm_sample": [u64, u64, i64, i64, vp, vp],
             "pcdm_kernel_time": [vp, ctypes.c_char_p, ctypes.POINTER(i64), pd],
+            "pcdm_set_rhs": [vp, vp, i32, vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)

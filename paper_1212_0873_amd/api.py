@@ -161,13 +161,48 @@ class Problem:
         return out
 
     def grad_backward(self, dL_dx):
-        """(dL/db [m] float64 host array, dL/dlambda) through the current iterate."""
-        g = np.ascontiguousarray(dL_dx, dtype=np.float64)
-        out = np.empty(self.m, dtype=np.float64)
+        """(dL/db, dL/dlambda) through the current iterate, taken as the
+        solution.  dL_dx: numpy array (result on the host) or CUDA tensor
+        (result a CUDA tensor)."""
         dl = ctypes.c_double()
-        check(self._lib.pcdm_grad_backward(self._h, g.ctypes.data, out.ctypes.data, ctypes.byref(dl), 0,
-                                           current_stream()))
+        if isinstance(dL_dx, np.ndarray):
+            g = np.ascontiguousarray(dL_dx, dtype=np.float64)
+            out = np.empty(self.m, dtype=np.float64)
+            check(self._lib.pcdm_grad_backward(self._h, g.ctypes.data, out.ctypes.data, ctypes.byref(dl), 0,
+                                               current_stream()))
+        else:
+            torch = _torch()
+            g = dL_dx.to(torch.float64).contiguous()
+            out = torch.empty(self.m, dtype=torch.float64, device=g.device)
+            check(self._lib.pcdm_grad_backward(self._h, g.data_ptr(), out.data_ptr(), ctypes.byref(dl), 1,
+                                               current_stream()))
         return out, dl.value
+
+    def set_rhs(self, b) -> None:
+        """Replace b (warm start: x and k are kept)."""
+        if isinstance(b, np.ndarray):
+            bb = np.ascontiguousarray(b, dtype=np.float64)
+            check(self._lib.pcdm_set_rhs(self._h, bb.ctypes.data, 0, current_stream()))
+        else:
+            bb = b.to(_torch().float64).contiguous()
+            check(self._lib.pcdm_set_rhs(self._h, bb.data_ptr(), 1, current_stream()))
+
+    def solve(self, rel_gap: float = 1e-6, check_every: int = 5, max_epochs: int = 100000) -> dict:
+        """Step until the certified duality gap (F - D)/D <= rel_gap; returns
+        {"epochs", "F", "gap", "rel_gap", "converged"}."""
+        spe = -(-self.n // self.info()["tau"])
+        epochs = 0
+        F = gap = None
+        rel = float("inf")
+        while epochs < max_epochs:
+            self.step(check_every * spe)
+            epochs += check_every
+            F, gap = self.objective(gap=True)
+            D = F - gap
+            rel = gap / max(abs(D), 1e-300)
+            if rel <= rel_gap:
+                break
+        return {"epochs": epochs, "F": F, "gap": gap, "rel_gap": rel, "converged": rel <= rel_gap}
 
 
 def sample(seed: int, k: int, tau: int, n: int):

@@ -765,4 +765,211 @@ k_sum_u64(const uint64_t *__restrict__ part, int nparts, Ctrl *__restrict__ ctrl
         ctrl->imax = (int64_t)s;
 }
 
+// --------------------------------------------------------------------------
+// Adjoint: PCDM on q(v) = 0.5 ||A_S v||^2 - g^T v over the active set S
+// (lambda = 0), with rho = A_S v kept in float64.  Coordinate c of the
+// sub-problem is column S[c].  Same sampler and tile reads as the step.
+// --------------------------------------------------------------------------
+
+// flags[i] = (x_i != 0)
+__global__ void __launch_bounds__(kBlock)
+k_flag_nonzero(const double *__restrict__ xm, int64_t n, uint8_t *__restrict__ flags)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        flags[i] = xm[i] != 0.0;
+}
+
+// gS[c] = g[S[c]]
+__global__ void __launch_bounds__(kBlock)
+k_gather_g(const int32_t *__restrict__ S, const double *__restrict__ g, int64_t ns, double *__restrict__ gS)
+{
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ns; c += (int64_t)gridDim.x * kBlock)
+        gS[c] = g[S[c]];
+}
+
+// Row histogram of the nonzeros of the columns in S (omega of the sub-problem).
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_adj_hist(const char *__restrict__ seg, Layout lay, const int32_t *__restrict__ S, int64_t ns,
+           int32_t *__restrict__ hist)
+{
+    using T = typename ValT<V>::T;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ns; c += (int64_t)gridDim.x * kBlock) {
+        int64_t off;
+        int32_t dp;
+        locate<V>(lay, S[c], off, dp);
+        const char *rows = seg + off + kHeader;
+        for (int e = 0; e < dp; e += 4) {
+            int rw[4];
+            T v[4];
+            Chunk4<V>::load(rows, dp, e, rw, v);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (v[t] != T(0))
+                    atomicAdd(hist + rw[t], 1);
+        }
+    }
+}
+
+// Phase 1 of an adjoint step: slot j takes c = pi(j) over [0, ns), column
+// S[c], partial derivative h = a^T rho - g_c, and v_c -= h / (beta_S L).
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_adj_gather(const char *__restrict__ seg, Layout lay, const int32_t *__restrict__ S,
+             const double *__restrict__ gS, double *__restrict__ vS, const double *__restrict__ rho,
+             int32_t *__restrict__ id_slot, double *__restrict__ delta_slot, uint64_t seed, uint64_t step,
+             int64_t tau, uint32_t ns, double inv_beta)
+{
+    using T = typename ValT<V>::T;
+    __shared__ uint32_t s_keys[kNiceRounds];
+    const NiceKey key = nice_key_block(seed, step, ns, s_keys);
+    const TileLanes<G> tl;
+    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64) {
+        const int64_t slot = base + tl.lane;
+        const bool act = slot < tau;
+        uint32_t c = 0;
+        int32_t col = 0;
+        int64_t off = 0;
+        int32_t dp = 0;
+        double il = 0.0;
+        if (act) {
+            c = nice_slot((uint32_t)slot, key);
+            col = S[c];
+            locate<V>(lay, col, off, dp);
+            il = reinterpret_cast<const double *>(seg + off)[1];
+        }
+        double acc[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            acc[q] = 0.0;
+        tile_entries<V, G>(seg, tl, off, dp, 0, [&](int q, int, int row, T val) {
+            acc[q] += (double)val * rho[row];
+        });
+        double mine = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double s = group_sum<G>(acc[q]);
+            const double got = __shfl(s, tl.leader_of_mine(q));
+            if (tl.lane / TileLanes<G>::CPR == q)
+                mine = got;
+        }
+        if (act) {
+            const double d = -(mine - gS[c]) * il * inv_beta;
+            vS[c] += d;
+            id_slot[slot] = col;
+            delta_slot[slot] = d;
+        }
+    }
+}
+
+// Phase 2 of an adjoint step: rho += delta a_col (float64 atomics).
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_adj_scatter(const char *__restrict__ seg, Layout lay, double *__restrict__ rho,
+              const int32_t *__restrict__ id_slot, const double *__restrict__ delta_slot, int64_t tau)
+{
+    using T = typename ValT<V>::T;
+    const TileLanes<G> tl;
+    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64) {
+        const int64_t slot = base + tl.lane;
+        const double d = slot < tau ? delta_slot[slot] : 0.0;
+        const bool live = d != 0.0;
+        if (!__any(live))
+            continue;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (live)
+            locate<V>(lay, id_slot[slot], off, dp);
+        tile_entries<V, G>(seg, tl, off, dp, d, [&](int, double dq, int row, T val) {
+            if (val != T(0))
+                atomic_add_hw<double>(rho + row, dq * (double)val);
+        });
+    }
+}
+
+// rho += v_c a_{S[c]} over all c (rho zeroed before): float64 A_S v.
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_adj_apply(const char *__restrict__ seg, Layout lay, const int32_t *__restrict__ S,
+            const double *__restrict__ vS, double *__restrict__ rho, int64_t ns)
+{
+    using T = typename ValT<V>::T;
+    const TileLanes<G> tl;
+    for (int64_t base = wave_global_id() * 64; base < ns; base += wave_count() * 64) {
+        const int64_t c = base + tl.lane;
+        const double w = c < ns ? vS[c] : 0.0;
+        const bool live = w != 0.0;
+        if (!__any(live))
+            continue;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (live)
+            locate<V>(lay, S[c], off, dp);
+        tile_entries<V, G>(seg, tl, off, dp, w, [&](int, double wq, int row, T val) {
+            if (val != T(0))
+                atomic_add_hw<double>(rho + row, wq * (double)val);
+        });
+    }
+}
+
+// part[blk] = max_c |a_{S[c]}^T rho - g_c| (residual of A_S^T A_S v = g).
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_adj_resid(const char *__restrict__ seg, Layout lay, const int32_t *__restrict__ S,
+            const double *__restrict__ gS, const double *__restrict__ rho, int64_t ns, double *__restrict__ part)
+{
+    using T = typename ValT<V>::T;
+    __shared__ double lds[kBlock];
+    const TileLanes<G> tl;
+    double best = 0.0;
+    for (int64_t base = wave_global_id() * 64; base < ns; base += wave_count() * 64) {
+        const int64_t c = base + tl.lane;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (c < ns)
+            locate<V>(lay, S[c], off, dp);
+        double acc[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            acc[q] = 0.0;
+        tile_entries<V, G>(seg, tl, off, dp, 0, [&](int q, int, int row, T val) {
+            acc[q] += (double)val * rho[row];
+        });
+        double mine = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double s = group_sum<G>(acc[q]);
+            const double got = __shfl(s, tl.leader_of_mine(q));
+            if (tl.lane / TileLanes<G>::CPR == q)
+                mine = got;
+        }
+        if (c < ns)
+            best = fmax(best, fabs(mine - gS[c]));
+    }
+    best = block_max_f64(best, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = best;
+}
+
+// part[3*blk] = partial sum of -sign(x_{S[c]}) v_c, part[3*blk+1] = max |g_c|.
+__global__ void __launch_bounds__(kBlock)
+k_adj_lambda(const int32_t *__restrict__ S, const double *__restrict__ xm, const double *__restrict__ vS,
+             const double *__restrict__ gS, int64_t ns, double *__restrict__ part)
+{
+    __shared__ double lds[kBlock];
+    double s = 0.0, gm = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ns; c += (int64_t)gridDim.x * kBlock) {
+        const double xv = xm[S[c]];
+        s -= (xv > 0.0 ? 1.0 : -1.0) * vS[c];
+        gm = fmax(gm, fabs(gS[c]));
+    }
+    s = block_sum_f64(s, lds);
+    gm = block_max_f64(gm, lds);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = s;
+        part[3 * blockIdx.x + 1] = gm;
+        part[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
 }  // namespace pcdm

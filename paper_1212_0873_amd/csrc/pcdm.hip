@@ -115,6 +115,14 @@ struct pcdm_problem {
 
     int timing = 0;
     KernelClock clocks[CLK_COUNT];
+
+    // adjoint solve settings
+    double adj_tol = 1e-6;
+    int64_t adj_max_epochs = 20000;
+    int64_t adj_tau = 0;  // 0 = the problem's tau
+    int64_t adj_check_every = 10;
+    int64_t adj_last_epochs = 0;
+    double adj_last_resid = 0.0;
     std::vector<hipEvent_t> event_pool;
 };
 
@@ -333,6 +341,38 @@ template <typename V> struct Ops {
                            P->ctrl->scal);
     }
 
+    static void adj_hist(pcdm_problem *P, const int32_t *S, int64_t ns, int32_t *hist, hipStream_t s)
+    {
+        const int g = grid_for(ns, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_adj_hist<V>), dim3(g), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, S, ns, hist);
+    }
+
+    static void adj_step(pcdm_problem *P, const int32_t *S, const double *gS, double *vS, double *rho,
+                         int32_t *ids, double *dels, uint64_t seed, uint64_t step, int64_t tau, int64_t ns,
+                         double inv_beta, hipStream_t s)
+    {
+        const int g = grid_for(tau, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_adj_gather<V, 8>), dim3(g), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, S, gS,
+                           vS, (const double *)rho, ids, dels, seed, step, tau, (uint32_t)ns, inv_beta);
+        hipLaunchKernelGGL((k_adj_scatter<V, 8>), dim3(g), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, rho,
+                           (const int32_t *)ids, (const double *)dels, tau);
+    }
+
+    // rho = A_S v, then ctrl->scal[4] = max_c |a_{S_c}^T rho - g_c|
+    static void adj_check(pcdm_problem *P, const int32_t *S, const double *gS, const double *vS, double *rho,
+                          int64_t ns, hipStream_t s)
+    {
+        const int gm = grid_for(P->m, kBlock, P->nblk_max);
+        const int g = grid_for(ns, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_fill<double>), dim3(gm), dim3(kBlock), 0, s, rho, 0.0, P->m);
+        hipLaunchKernelGGL((k_adj_apply<V, 8>), dim3(g), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, S, vS,
+                           rho, ns);
+        hipLaunchKernelGGL((k_adj_resid<V, 8>), dim3(g), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, S, gS,
+                           (const double *)rho, ns, P->part2);
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, g, 1, 1,
+                           P->ctrl->scal + 4);
+    }
+
     static void x_to_records(pcdm_problem *P, hipStream_t s)
     {
         const int g = grid_for(P->n, kBlock, P->nblk_max);
@@ -367,6 +407,27 @@ int check_launch(const char *what)
         return hip_fail(e, what);
     return PCDM_OK;
 }
+
+// Device temporaries of one call, freed when it returns.
+struct DevTemps {
+    std::vector<void *> p;
+    ~DevTemps()
+    {
+        for (void *q : p)
+            if (q)
+                (void)hipFree(q);
+    }
+    template <typename T> int get(T **out, size_t bytes)
+    {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess)
+            return hip_fail(e, "temporary allocation");
+        p.push_back(q);
+        *out = (T *)q;
+        return PCDM_OK;
+    }
+};
 
 int refresh_now(pcdm_problem *P, hipStream_t s)
 {
@@ -639,6 +700,22 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             h->chunks = c;
             h->lanes_auto = 0;
         }
+    } else if (k == "adj_tol") {
+        if (!(value > 0.0))
+            return fail(PCDM_EINVAL, "adj_tol must be > 0");
+        h->adj_tol = value;
+    } else if (k == "adj_max_epochs") {
+        if (!(value >= 1.0))
+            return fail(PCDM_EINVAL, "adj_max_epochs must be >= 1");
+        h->adj_max_epochs = (int64_t)value;
+    } else if (k == "adj_tau") {
+        if (!(value >= 0.0))
+            return fail(PCDM_EINVAL, "adj_tau must be >= 0");
+        h->adj_tau = (int64_t)value;
+    } else if (k == "adj_check_every") {
+        if (!(value >= 1.0))
+            return fail(PCDM_EINVAL, "adj_check_every must be >= 1");
+        h->adj_check_every = (int64_t)value;
     } else if (k == "kernel_timing") {
         for (int c = 0; c < CLK_COUNT; ++c) {
             PCDM_TRY(clock_collect(h, c));
@@ -843,14 +920,138 @@ int pcdm_get_residual(pcdm_problem *h, double *r_out, int32_t on_device, void *s
 int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db, double *dL_dlambda,
                        int32_t on_device, void *stream)
 {
-    (void)dL_dx;
-    (void)dL_db;
-    (void)dL_dlambda;
-    (void)on_device;
-    (void)stream;
-    if (!h)
-        return fail(PCDM_EINVAL, "NULL handle");
-    return fail(PCDM_ESTATE, "pcdm_grad_backward: not available in this build");
+    if (!h || !dL_dx || !dL_db || !dL_dlambda)
+        return fail(PCDM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    const int64_t n = h->n, m = h->m;
+    DevTemps tmp;  // freed on every exit
+    double *g = nullptr, *gS = nullptr, *vS = nullptr, *rho = nullptr, *dels = nullptr;
+    uint8_t *flags = nullptr;
+    int32_t *S = nullptr, *ids = nullptr, *hist = nullptr, *nsel = nullptr;
+    PCDM_TRY(tmp.get(&g, (size_t)n * 8));
+    PCDM_TRY(tmp.get(&flags, (size_t)n));
+    PCDM_TRY(tmp.get(&S, (size_t)n * 4));
+    PCDM_TRY(tmp.get(&nsel, 16));
+    PCDM_TRY(tmp.get(&rho, (size_t)m * 8));
+    HIP_TRY(hipMemcpyAsync(g, dL_dx, (size_t)n * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+
+    // active set S = {i : x_i != 0}, ascending
+    const int gn = grid_for(n, kBlock, h->nblk_max);
+    hipLaunchKernelGGL(k_flag_nonzero, dim3(gn), dim3(kBlock), 0, s, (const double *)h->x, n, flags);
+    size_t tb = 0;
+    hipcub::CountingInputIterator<int32_t> count_it(0);
+    HIP_TRY(hipcub::DeviceSelect::Flagged(nullptr, tb, count_it, flags, S, nsel, (int)n, s));
+    void *tstore = nullptr;
+    PCDM_TRY(tmp.get(&tstore, tb));
+    HIP_TRY(hipcub::DeviceSelect::Flagged(tstore, tb, count_it, flags, S, nsel, (int)n, s));
+    int32_t ns32 = 0;
+    HIP_TRY(hipMemcpyAsync(&ns32, nsel, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t ns = ns32;
+    const int gm = grid_for(m, kBlock, h->nblk_max);
+    if (ns == 0) {
+        hipLaunchKernelGGL((k_fill<double>), dim3(gm), dim3(kBlock), 0, s, rho, 0.0, m);
+        HIP_TRY(hipMemcpyAsync(dL_db, rho, (size_t)m * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *dL_dlambda = 0.0;
+        h->adj_last_epochs = 0;
+        h->adj_last_resid = 0.0;
+        return PCDM_OK;
+    }
+    const int64_t tau_s = std::min<int64_t>(h->adj_tau > 0 ? h->adj_tau : h->tau, ns);
+    PCDM_TRY(tmp.get(&gS, (size_t)ns * 8));
+    PCDM_TRY(tmp.get(&vS, (size_t)ns * 8));
+    PCDM_TRY(tmp.get(&hist, (size_t)m * 4));
+    PCDM_TRY(tmp.get(&ids, (size_t)tau_s * 4));
+    PCDM_TRY(tmp.get(&dels, (size_t)tau_s * 8));
+    const int gs = grid_for(ns, kBlock, h->nblk_max);
+    hipLaunchKernelGGL(k_gather_g, dim3(gs), dim3(kBlock), 0, s, (const int32_t *)S, (const double *)g, ns, gS);
+    hipLaunchKernelGGL((k_fill<double>), dim3(gs), dim3(kBlock), 0, s, vS, 0.0, ns);
+    hipLaunchKernelGGL((k_fill<double>), dim3(gm), dim3(kBlock), 0, s, rho, 0.0, m);
+    hipLaunchKernelGGL((k_fill<int32_t>), dim3(gm), dim3(kBlock), 0, s, hist, 0, m);
+    PCDM_TRY(dispatch(h->dtype, [&](auto ops) {
+        decltype(ops)::adj_hist(h, S, ns, hist, s);
+        return PCDM_OK;
+    }));
+    hipLaunchKernelGGL(k_imax_partials, dim3(gm), dim3(kBlock), 0, s, (const int32_t *)hist, m, (int64_t *)h->part2);
+    hipLaunchKernelGGL(k_imax_final, dim3(1), dim3(kBlock), 0, s, (const int64_t *)h->part2, gm, h->ctrl);
+    hipLaunchKernelGGL(k_adj_lambda, dim3(kReduceBlocks), dim3(kBlock), 0, s, (const int32_t *)S, (const double *)h->x,
+                       (const double *)vS, (const double *)gS, ns, h->part);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)h->part, kReduceBlocks, 3, 1,
+                       h->ctrl->scal);  // scal[1] = max |g_S|
+    PCDM_TRY(check_launch("adjoint set-up"));
+    Ctrl hc;
+    HIP_TRY(hipMemcpyAsync(&hc, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t omega_s = std::max<int64_t>(hc.imax, 1);
+    const double gmax = hc.scal[1];
+    const double beta_s = 1.0 + (double)(omega_s - 1) * (double)(tau_s - 1) / std::max(1.0, (double)ns - 1.0);
+    const int64_t spe = ceil_div(ns, tau_s);
+    const uint64_t seed_adj = h->seed ^ 0xAD101E5EEDull;
+    double resid = gmax;
+    bool converged = gmax == 0.0;
+    int64_t epoch = 0;
+    uint64_t step = 0;
+    while (!converged && epoch < h->adj_max_epochs) {
+        for (int64_t q = 0; q < spe; ++q, ++step)
+            dispatch(h->dtype, [&](auto ops) {
+                decltype(ops)::adj_step(h, S, gS, vS, rho, ids, dels, seed_adj, step, tau_s, ns, 1.0 / beta_s, s);
+                return PCDM_OK;
+            });
+        ++epoch;
+        if (epoch % h->adj_check_every == 0 || epoch == h->adj_max_epochs) {
+            dispatch(h->dtype, [&](auto ops) {
+                decltype(ops)::adj_check(h, S, gS, vS, rho, ns, s);
+                return PCDM_OK;
+            });
+            PCDM_TRY(check_launch("adjoint check"));
+            double r4 = 0.0;
+            HIP_TRY(hipMemcpyAsync(&r4, h->ctrl->scal + 4, 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            resid = r4;
+            converged = resid <= h->adj_tol * gmax;
+        }
+    }
+    // the loop ends at a check (or with v = 0), so rho = A_S v is fresh
+    // dL/db = A_S v (rho, fresh after the last check), dL/dlambda = -s^T v
+    hipLaunchKernelGGL(k_adj_lambda, dim3(kReduceBlocks), dim3(kBlock), 0, s, (const int32_t *)S, (const double *)h->x,
+                       (const double *)vS, (const double *)gS, ns, h->part);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)h->part, kReduceBlocks, 3, 0,
+                       h->ctrl->scal);  // scal[0] = -s^T v
+    PCDM_TRY(check_launch("adjoint outputs"));
+    HIP_TRY(hipMemcpyAsync(dL_db, rho, (size_t)m * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    double lam_grad = 0.0;
+    HIP_TRY(hipMemcpyAsync(&lam_grad, h->ctrl->scal, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *dL_dlambda = lam_grad;
+    h->adj_last_epochs = epoch;
+    h->adj_last_resid = gmax > 0.0 ? resid / gmax : 0.0;
+    if (!converged)
+        return fail(PCDM_ENOTCONV, "adjoint solve stopped at relative normal-equation residual " +
+                                       std::to_string(h->adj_last_resid) + " after " + std::to_string(epoch) +
+                                       " epochs");
+    return PCDM_OK;
+}
+
+int pcdm_set_rhs(pcdm_problem *h, const double *b, int32_t on_device, void *stream)
+{
+    if (!h || !b)
+        return fail(PCDM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    HIP_TRY(hipMemcpyAsync(h->b64, b, (size_t)h->m * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    PCDM_TRY(refresh_now(h, s));
+    // ||A^T b||_inf for callers that set lambda relative to it
+    const int gm = grid_for(h->m, kBlock, h->nblk_max);
+    hipLaunchKernelGGL(k_neg_copy, dim3(gm), dim3(kBlock), 0, s, (const double *)h->b64, h->r64, h->m);
+    PCDM_TRY(dispatch(h->dtype, [&](auto ops) { return decltype(ops)::atr_absmax(h, h->r64, s); }));
+    PCDM_TRY(check_launch("pcdm_set_rhs"));
+    double c = 0.0;
+    HIP_TRY(hipMemcpyAsync(&c, h->ctrl->scal + 3, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->atb_inf = c;
+    return PCDM_OK;
 }
 
 int pcdm_kernel_time(pcdm_problem *h, const char *kernel, int64_t *launches, double *total_ms)
