@@ -218,12 +218,67 @@ int pcdm_set_rhs(pcdm_problem *h, const double *b, int32_t on_device, void *stre
 int pcdm_kernel_time(pcdm_problem *h, const char *kernel, int64_t *launches, double *total_ms);
 
 /*
+ * Schedule autotuner: runs steps_per_candidate real steps (they advance k)
+ * with each supported (lanes_per_column, chunks_per_lane) pair, timed with
+ * HIP events on `stream`, and keeps the fastest.  Synchronous.
+ */
+int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream);
+
+/*
  * The tau-nice sampler on its own: writes S_k = {pi_k(j) : 0 <= j < tau}
  * for key (seed, k) into out_device[0..tau) (int32, device memory), in slot
  * order.  Same sets as pcdm_step draws.  Asynchronous.
  */
 int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device,
                 void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solver: many independent LASSO problems (uneven m_j, n_j, a
+ * lambda grid, several right-hand sides) advanced together, one launch per
+ * phase for all of them.  Problem j uses the tau-nice sampler with key
+ * (seed + j, k_j), its own beta_j (from its omega_j and tau_j), its own
+ * float64 refresh every ceil(n_j/tau_j) steps, and converges exactly as it
+ * would alone (same steps, same sets).  Problems can be retired (held
+ * still) once solved.
+ * ------------------------------------------------------------------------ */
+typedef struct pcdm_batch pcdm_batch; /* opaque, owned by the library */
+
+/* Create from `count` problems: A[j], b[j] ([m_j] float64), lambda[j],
+ * tau[j].  All A[j] share one dtype and one memory kind (on_device), which
+ * b follows.  Validation as in pcdm_create (errors name the problem).
+ * Synchronous on the default stream. */
+int pcdm_batch_create(int count, const pcdm_csc *A, const double *const *b, const double *lambda,
+                      const int64_t *tau, uint64_t seed, pcdm_batch **out);
+
+/* Advance every active problem by nsteps steps.  Runs of "graph_steps"
+ * (option, default 32; 0 disables) steps are captured once into a HIP graph
+ * and replayed; the remainder is launched directly.  Asynchronous. */
+int pcdm_batch_step(pcdm_batch *B, int64_t nsteps, void *stream);
+
+/* F_j and (if gap != NULL) the duality gap of every problem, float64
+ * (arrays of `count`).  Synchronous. */
+int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream);
+
+/* active[j] = 0 holds problem j still (retired), 1 resumes it.  Synchronises the device. */
+int pcdm_batch_set_active(pcdm_batch *B, const int32_t *active);
+
+/* x of problem `index` (n_index float64 values, host or device). */
+int pcdm_batch_get_x(pcdm_batch *B, int index, double *x_out, int32_t on_device, void *stream);
+
+/* Sizes, omega, beta, lambda, ||A^T b||_inf, steps taken of problem `index`
+ * (nonzero_updates is -1: not tracked per problem). */
+int pcdm_batch_get_info(pcdm_batch *B, int index, pcdm_info *out);
+
+/* Options: "graph_steps" (>= 0), "lanes_per_column", "chunks_per_lane"
+ * (pairs as for pcdm_set_option). */
+int pcdm_batch_set_option(pcdm_batch *B, const char *key, double value);
+
+/* Schedule autotuner for the batch (as pcdm_autotune; the steps advance
+ * every active problem). */
+int pcdm_batch_autotune(pcdm_batch *B, int64_t steps_per_candidate, void *stream);
+
+/* Free (synchronises the device). NULL is a no-op. */
+int pcdm_batch_destroy(pcdm_batch *B);
 
 #ifdef __cplusplus
 }

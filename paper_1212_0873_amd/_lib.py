@@ -17,7 +17,10 @@ STATUS_NAMES = {0: "PCDM_OK", -1: "PCDM_EINVAL", -2: "PCDM_ENOMEM", -3: "PCDM_ED
 # every symbol include/pcdm.h declares
 EXPORTS = ("pcdm_create", "pcdm_destroy", "pcdm_last_error", "pcdm_set_option", "pcdm_get_info",
            "pcdm_step", "pcdm_objective", "pcdm_get_x", "pcdm_set_x", "pcdm_get_residual",
-           "pcdm_grad_backward", "pcdm_set_rhs", "pcdm_kernel_time", "pcdm_sample")
+           "pcdm_grad_backward", "pcdm_set_rhs", "pcdm_kernel_time", "pcdm_autotune", "pcdm_sample",
+           "pcdm_batch_create", "pcdm_batch_step", "pcdm_batch_objective", "pcdm_batch_set_active",
+           "pcdm_batch_get_x", "pcdm_batch_get_info", "pcdm_batch_set_option", "pcdm_batch_autotune",
+           "pcdm_batch_destroy")
 
 
 class pcdm_csc(ctypes.Structure):
@@ -71,6 +74,17 @@ def load() -> ctypes.CDLL:
             "pcdm_sample": [u64, u64, i64, i64, vp, vp],
             "pcdm_kernel_time": [vp, ctypes.c_char_p, ctypes.POINTER(i64), pd],
             "pcdm_set_rhs": [vp, vp, i32, vp],
+            "pcdm_autotune": [vp, i64, vp],
+            "pcdm_batch_create": [ctypes.c_int, ctypes.POINTER(pcdm_csc), ctypes.POINTER(vp), pd,
+                                  ctypes.POINTER(i64), u64, ctypes.POINTER(vp)],
+            "pcdm_batch_step": [vp, i64, vp],
+            "pcdm_batch_objective": [vp, pd, pd, vp],
+            "pcdm_batch_set_active": [vp, ctypes.POINTER(i32)],
+            "pcdm_batch_get_x": [vp, ctypes.c_int, vp, i32, vp],
+            "pcdm_batch_get_info": [vp, ctypes.c_int, ctypes.POINTER(pcdm_info)],
+            "pcdm_batch_set_option": [vp, ctypes.c_char_p, f64],
+            "pcdm_batch_autotune": [vp, i64, vp],
+            "pcdm_batch_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)

@@ -119,6 +119,12 @@ class Problem:
         d["lambda"] = d.pop("lambda_")
         return d
 
+    def autotune(self, steps_per_candidate: int = 5) -> dict:
+        """Time every supported schedule for a few real steps and keep the fastest."""
+        check(self._lib.pcdm_autotune(self._h, int(steps_per_candidate), current_stream()))
+        inf = self.info()
+        return {"lanes_per_column": inf["lanes_per_column"], "chunks_per_lane": inf["chunks_per_lane"]}
+
     def kernel_time(self, kernel: str):
         """(launches, total milliseconds) of one kernel kind while timing is on."""
         n = ctypes.c_int64()
@@ -212,3 +218,107 @@ def sample(seed: int, k: int, tau: int, n: int):
     check(load().pcdm_sample(int(seed) & (2**64 - 1), int(k), int(tau), int(n), out.data_ptr(),
                              current_stream()))
     return out[: int(tau)]
+
+
+class Batch:
+    """Many independent LASSO problems advanced together (``pcdm_batch_*``).
+
+    ``problems``: a list of (A, b, lam, tau) with host numpy CSCs of one
+    dtype.  Problem j samples with key (seed + j, k_j)."""
+
+    def __init__(self, problems, seed: int = 0):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        cnt = len(problems)
+        descs = (pcdm_csc * cnt)()
+        keep = []
+        bptr = (ctypes.c_void_p * cnt)()
+        lams = (ctypes.c_double * cnt)()
+        taus = (ctypes.c_int64 * cnt)()
+        for j, (A, b, lam, tau) in enumerate(problems):
+            vals = np.ascontiguousarray(A.values)
+            cp = np.ascontiguousarray(A.col_ptr, dtype=np.int64)
+            ri = np.ascontiguousarray(A.row_idx, dtype=np.int32)
+            bb = np.ascontiguousarray(b, dtype=np.float64)
+            keep += [vals, cp, ri, bb]
+            descs[j] = pcdm_csc(int(A.m), int(A.n), int(vals.size), cp.ctypes.data, ri.ctypes.data,
+                                vals.ctypes.data, _NP_DTYPE[vals.dtype], 0)
+            bptr[j] = bb.ctypes.data
+            lams[j] = float(lam)
+            taus[j] = int(tau)
+        check(self._lib.pcdm_batch_create(cnt, descs, bptr, lams, taus, int(seed) & (2**64 - 1),
+                                          ctypes.byref(self._h)))
+        self.count = cnt
+        self.ns = [int(p[0].n) for p in problems]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            check(self._lib.pcdm_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, nsteps: int = 1) -> None:
+        check(self._lib.pcdm_batch_step(self._h, int(nsteps), current_stream()))
+
+    def objective(self):
+        F = (ctypes.c_double * self.count)()
+        G = (ctypes.c_double * self.count)()
+        check(self._lib.pcdm_batch_objective(self._h, F, G, current_stream()))
+        return np.array(F[:]), np.array(G[:])
+
+    def set_active(self, flags) -> None:
+        arr = (ctypes.c_int32 * self.count)(*[1 if f else 0 for f in flags])
+        check(self._lib.pcdm_batch_set_active(self._h, arr))
+
+    def get_x(self, j: int) -> np.ndarray:
+        out = np.empty(self.ns[j], dtype=np.float64)
+        check(self._lib.pcdm_batch_get_x(self._h, int(j), out.ctypes.data, 0, current_stream()))
+        return out
+
+    def info(self, j: int) -> dict:
+        inf = pcdm_info()
+        check(self._lib.pcdm_batch_get_info(self._h, int(j), ctypes.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in pcdm_info._fields_}
+        d["lambda"] = d.pop("lambda_")
+        return d
+
+    def set_option(self, key: str, value: float) -> None:
+        check(self._lib.pcdm_batch_set_option(self._h, key.encode(), float(value)))
+
+    def autotune(self, steps_per_candidate: int = 3) -> dict:
+        check(self._lib.pcdm_batch_autotune(self._h, int(steps_per_candidate), current_stream()))
+        inf = self.info(0)
+        return {"lanes_per_column": inf["lanes_per_column"], "chunks_per_lane": inf["chunks_per_lane"]}
+
+    def solve(self, rel_gap: float = 1e-6, check_every_steps: int = 64, max_steps: int = 10**7) -> dict:
+        """Step all problems, retiring each once its certified gap
+        (F - D)/D <= rel_gap; returns per-problem steps and gaps."""
+        active = [True] * self.count
+        done_at = [None] * self.count
+        steps = 0
+        rel = np.full(self.count, np.inf)
+        while any(active) and steps < max_steps:
+            self.step(check_every_steps)
+            steps += check_every_steps
+            F, gap = self.objective()
+            rel = gap / np.maximum(np.abs(F - gap), 1e-300)
+            changed = False
+            for j in range(self.count):
+                if active[j] and rel[j] <= rel_gap:
+                    active[j] = False
+                    done_at[j] = steps
+                    changed = True
+            if changed:
+                self.set_active(active)
+        return {"steps": steps, "done_at": done_at, "rel_gap": rel.tolist(), "converged": not any(active)}

@@ -258,9 +258,134 @@ __device__ __forceinline__ void tile_entries(const char *__restrict__ seg, const
 // The step.
 // --------------------------------------------------------------------------
 
-// Phase 1 of step k: slot j < tau takes i = pi_k(j), g_i = a_i^T r (working
-// precision T) and the damped soft-threshold update of x_i in float64;
-// records (i, delta_i) in slot j and writes x_i (record and mirror).
+// One tile of phase 1: slots base .. base+63 of a step with sampler key
+// `key`.  Slot j takes i = pi_k(j), g_i = a_i^T r (working precision T) and
+// the damped soft-threshold update of x_i in float64; records (i, delta_i) in
+// slot j and writes x_i (record and mirror).  Pointers are the problem's own.
+template <typename V, int G, int C>
+__device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout &lay,
+                                            const typename ValT<V>::T *__restrict__ r, double *__restrict__ xm,
+                                            int32_t *__restrict__ id_slot,
+                                            typename ValT<V>::T *__restrict__ delta_slot, const NiceKey &key,
+                                            const TileLanes<G> &tl, int64_t base, int64_t tau, double inv_beta,
+                                            double lam, uint64_t &nz)
+{
+    using T = typename ValT<V>::T;
+    const int64_t slot = base + tl.lane;
+    const bool act = slot < tau;
+    uint32_t i = 0;
+    int64_t off = 0;
+    int32_t dp = 0;
+    double xi = 0.0, il = 0.0;
+    if (act) {
+        i = nice_slot((uint32_t)slot, key);
+        locate<V>(lay, i, off, dp);
+        const double *hdr = reinterpret_cast<const double *>(seg + off);
+        xi = hdr[0];
+        il = hdr[1];
+    }
+    // rounds in batches of RB so that at most PCDM_CHUNK_BUDGET chunks per lane are live
+    constexpr int RB = (G < PCDM_CHUNK_BUDGET / C) ? G : (PCDM_CHUNK_BUDGET / C > 0 ? PCDM_CHUNK_BUDGET / C : 1);
+    T mine = T(0);
+#pragma unroll(G == RB ? 1 : 2)
+    for (int q0 = 0; q0 < G; q0 += RB) {
+        int64_t qoff[RB];
+        int32_t qdp[RB];
+        int rw[RB][C][4];
+        T v[RB][C][4];
+#pragma unroll
+        for (int qq = 0; qq < RB; ++qq) {
+            const int q = q0 + qq;
+            qoff[qq] = __shfl(off, tl.owner(q));
+            qdp[qq] = __shfl(dp, tl.owner(q));
+            const char *rows = seg + qoff[qq] + kHeader;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int e = 4 * (tl.gl + G * c);
+                if (e < qdp[qq]) {
+                    Chunk4<V>::load(rows, qdp[qq], e, rw[qq][c], v[qq][c]);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        rw[qq][c][t] = 0;
+                        v[qq][c][t] = T(0);
+                    }
+                }
+            }
+        }
+        T acc[RB];
+#pragma unroll
+        for (int qq = 0; qq < RB; ++qq) {
+            acc[qq] = T(0);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (4 * (tl.gl + G * c) < qdp[qq]) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[qq] += v[qq][c][t] * load_row(r, rw[qq][c][t]);
+                }
+            }
+        }
+#pragma unroll
+        for (int qq = 0; qq < RB; ++qq) {
+            const char *rows = seg + qoff[qq] + kHeader;
+            for (int e = 4 * (tl.gl + G * C); e < qdp[qq]; e += 4 * G) {
+                int rr[4];
+                T vv[4];
+                Chunk4<V>::load(rows, qdp[qq], e, rr, vv);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[qq] += vv[t] * load_row(r, rr[t]);
+            }
+        }
+#pragma unroll
+        for (int qq = 0; qq < RB; ++qq) {
+            const int q = q0 + qq;
+            const T sum = group_sum<G>(acc[qq]);
+            const T got = __shfl(sum, tl.leader_of_mine(q));
+            if (tl.lane / TileLanes<G>::CPR == q)
+                mine = got;
+        }
+    }
+    if (act) {
+        const double scale = il * inv_beta;  // 1 / (beta L_i)
+        const double xn = soft_threshold<double>(xi - (double)mine * scale, lam * scale);
+        const double d = xn - xi;
+        id_slot[slot] = (int32_t)i;
+        delta_slot[slot] = (T)d;
+        if (d != 0.0) {
+            *reinterpret_cast<double *>(seg + off) = xn;
+            xm[i] = xn;
+            ++nz;
+        }
+    }
+}
+
+// One tile of phase 2: r += delta_i a_i for the tile's slots with delta_i != 0.
+template <typename V, int G>
+__device__ __forceinline__ void scatter_tile(const char *__restrict__ seg, const Layout &lay,
+                                             typename ValT<V>::T *__restrict__ r,
+                                             const int32_t *__restrict__ id_slot,
+                                             const typename ValT<V>::T *__restrict__ delta_slot,
+                                             const TileLanes<G> &tl, int64_t base, int64_t tau)
+{
+    using T = typename ValT<V>::T;
+    const int64_t slot = base + tl.lane;
+    const T d = slot < tau ? delta_slot[slot] : T(0);
+    const bool live = d != T(0);
+    if (!__any(live))
+        return;
+    int64_t off = 0;
+    int32_t dp = 0;
+    if (live)
+        locate<V>(lay, id_slot[slot], off, dp);
+    tile_entries<V, G>(seg, tl, off, dp, d, [&](int, T dq, int row, T val) {
+        if (val != T(0))
+            atomic_add_hw<T>(r + row, dq * val);
+    });
+}
+
+// Phase 1 of step k over all tiles of one problem.
 template <typename V, int G, int C>
 __global__ void __launch_bounds__(kBlock)
 k_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
@@ -268,104 +393,13 @@ k_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restri
          const Ctrl *__restrict__ ctrl, uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau,
          uint32_t n, double inv_beta, double lam)
 {
-    using T = typename ValT<V>::T;
     __shared__ uint32_t s_keys[kNiceRounds];
     __shared__ uint64_t s_red[kBlock / 64];
-
     const NiceKey key = nice_key_block(seed, ctrl->k, n, s_keys);
     const TileLanes<G> tl;
     uint64_t nz = 0;
-
-    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64) {
-        const int64_t slot = base + tl.lane;
-        const bool act = slot < tau;
-        uint32_t i = 0;
-        int64_t off = 0;
-        int32_t dp = 0;
-        double xi = 0.0, il = 0.0;
-        if (act) {
-            i = nice_slot((uint32_t)slot, key);
-            locate<V>(lay, i, off, dp);
-            const double *hdr = reinterpret_cast<const double *>(seg + off);
-            xi = hdr[0];
-            il = hdr[1];
-        }
-        // rounds in batches of RB so that at most 8 chunks per lane are live
-        constexpr int RB = (G < PCDM_CHUNK_BUDGET / C) ? G : (PCDM_CHUNK_BUDGET / C > 0 ? PCDM_CHUNK_BUDGET / C : 1);
-        T mine = T(0);
-#pragma unroll(G == RB ? 1 : 2)
-        for (int q0 = 0; q0 < G; q0 += RB) {
-            int64_t qoff[RB];
-            int32_t qdp[RB];
-            int rw[RB][C][4];
-            T v[RB][C][4];
-#pragma unroll
-            for (int qq = 0; qq < RB; ++qq) {
-                const int q = q0 + qq;
-                qoff[qq] = __shfl(off, tl.owner(q));
-                qdp[qq] = __shfl(dp, tl.owner(q));
-                const char *rows = seg + qoff[qq] + kHeader;
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const int e = 4 * (tl.gl + G * c);
-                    if (e < qdp[qq]) {
-                        Chunk4<V>::load(rows, qdp[qq], e, rw[qq][c], v[qq][c]);
-                    } else {
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            rw[qq][c][t] = 0;
-                            v[qq][c][t] = T(0);
-                        }
-                    }
-                }
-            }
-            T acc[RB];
-#pragma unroll
-            for (int qq = 0; qq < RB; ++qq) {
-                acc[qq] = T(0);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    if (4 * (tl.gl + G * c) < qdp[qq]) {
-#pragma unroll
-                        for (int t = 0; t < 4; ++t)
-                            acc[qq] += v[qq][c][t] * load_row(r, rw[qq][c][t]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int qq = 0; qq < RB; ++qq) {
-                const char *rows = seg + qoff[qq] + kHeader;
-                for (int e = 4 * (tl.gl + G * C); e < qdp[qq]; e += 4 * G) {
-                    int rr[4];
-                    T vv[4];
-                    Chunk4<V>::load(rows, qdp[qq], e, rr, vv);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        acc[qq] += vv[t] * load_row(r, rr[t]);
-                }
-            }
-#pragma unroll
-            for (int qq = 0; qq < RB; ++qq) {
-                const int q = q0 + qq;
-                const T sum = group_sum<G>(acc[qq]);
-                const T got = __shfl(sum, tl.leader_of_mine(q));
-                if (tl.lane / TileLanes<G>::CPR == q)
-                    mine = got;
-            }
-        }
-        if (act) {
-            const double scale = il * inv_beta;  // 1 / (beta L_i)
-            const double xn = soft_threshold<double>(xi - (double)mine * scale, lam * scale);
-            const double d = xn - xi;
-            id_slot[slot] = (int32_t)i;
-            delta_slot[slot] = (T)d;
-            if (d != 0.0) {
-                *reinterpret_cast<double *>(seg + off) = xn;
-                xm[i] = xn;
-                ++nz;
-            }
-        }
-    }
+    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64)
+        gather_tile<V, G, C>(seg, lay, r, xm, id_slot, delta_slot, key, tl, base, tau, inv_beta, lam, nz);
     const uint64_t tot = block_sum_u64(nz, s_red);
     if (threadIdx.x == 0 && tot)
         nz_part[blockIdx.x] += tot;
@@ -380,25 +414,11 @@ k_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restr
           const int32_t *__restrict__ id_slot, const typename ValT<V>::T *__restrict__ delta_slot,
           Ctrl *__restrict__ ctrl, int64_t tau)
 {
-    using T = typename ValT<V>::T;
     if (blockIdx.x == 0 && threadIdx.x == 0)
         ctrl->k += 1;  // no block of this kernel reads k
     const TileLanes<G> tl;
-    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64) {
-        const int64_t slot = base + tl.lane;
-        const T d = slot < tau ? delta_slot[slot] : T(0);
-        const bool live = d != T(0);
-        if (!__any(live))
-            continue;
-        int64_t off = 0;
-        int32_t dp = 0;
-        if (live)
-            locate<V>(lay, id_slot[slot], off, dp);
-        tile_entries<V, G>(seg, tl, off, dp, d, [&](int, T dq, int row, T val) {
-            if (val != T(0))
-                atomic_add_hw<T>(r + row, dq * val);
-        });
-    }
+    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64)
+        scatter_tile<V, G>(seg, lay, r, id_slot, delta_slot, tl, base, tau);
 }
 
 // The sampler alone (for tests and callers that want S_k).

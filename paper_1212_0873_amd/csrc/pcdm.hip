@@ -1068,6 +1068,47 @@ int pcdm_kernel_time(pcdm_problem *h, const char *kernel, int64_t *launches, dou
     return PCDM_OK;
 }
 
+int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream)
+{
+    if (!h || steps_per_candidate < 1)
+        return fail(PCDM_EINVAL, "NULL handle or steps_per_candidate < 1");
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    static const int cand[][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {8, 1}, {8, 2}, {16, 1}};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = std::numeric_limits<float>::max();
+    int bg = h->lanes, bc = h->chunks;
+    int st = PCDM_OK;
+    const int keep_timing = h->timing;
+    h->timing = 0;
+    for (const auto &c : cand) {
+        h->lanes = c[0];
+        h->chunks = c[1];
+        (void)hipEventRecord(e0, s);
+        st = pcdm_step(h, steps_per_candidate, stream);
+        (void)hipEventRecord(e1, s);
+        if (st != PCDM_OK)
+            break;
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            break;
+        if (ms < best) {
+            best = ms;
+            bg = c[0];
+            bc = c[1];
+        }
+    }
+    h->timing = keep_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->lanes = bg;
+    h->chunks = bc;
+    h->lanes_auto = 0;
+    return st;
+}
+
 int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device, void *stream)
 {
     if (!out_device)
@@ -1083,3 +1124,5 @@ int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_
 }
 
 }  // extern "C"
+
+#include "batch_runtime.hpp"

@@ -104,4 +104,22 @@ __device__ __forceinline__ NiceKey nice_key_block(uint64_t seed, uint64_t step, 
     return key;
 }
 
+// Per-wave variant (a block may serve several problems): lanes 0..9 derive
+// the round keys, which are then broadcast across the wave.
+__device__ __forceinline__ NiceKey nice_key_wave(uint64_t seed, uint64_t step, uint32_t n)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t mine = 0;
+    if (lane < kNiceRounds)
+        mine = (uint32_t)splitmix_output(seed ^ kNiceStream, step * kNiceRounds + lane);
+    NiceKey key;
+#pragma unroll
+    for (int q = 0; q < kNiceRounds; ++q)
+        key.rk[q] = (uint32_t)__shfl((int)mine, q);
+    key.half = nice_half_width(n);
+    key.mask = (1u << key.half) - 1u;
+    key.n = n;
+    return key;
+}
+
 }  // namespace pcdm
