@@ -287,7 +287,8 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
     // rounds in batches of RB so that at most PCDM_CHUNK_BUDGET chunks per lane are live
     constexpr int RB = (G < PCDM_CHUNK_BUDGET / C) ? G : (PCDM_CHUNK_BUDGET / C > 0 ? PCDM_CHUNK_BUDGET / C : 1);
     T mine = T(0);
-#pragma unroll(G == RB ? 1 : 2)
+    constexpr int kUnroll = (G == RB) ? 1 : 2;
+#pragma unroll kUnroll
     for (int q0 = 0; q0 < G; q0 += RB) {
         int64_t qoff[RB];
         int32_t qdp[RB];

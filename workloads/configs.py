@@ -35,9 +35,10 @@ CONFIGS: Dict[str, dict] = {
     "train_1e5x1e6": dict(m=100_000, n=1_000_000, d=10, balanced=False, normalize=False,
                xstar_nnz=2000, noise_std=0.1, lam_factor=0.1, taus=(4096,)),
     # big single-GPU instance: 2e8 x 5e8, 20 nnz/col, balanced slots
+    # built on the device by the counter-based recipe of workloads/csrc/gen_common.h
     "lasso_2e8x5e8": dict(m=200_000_000, n=500_000_000, d=20, balanced=True, normalize=True,
                xstar_nnz=100_000, noise_std=1e-2, lam_factor=0.05,
-               taus=(65536, 1 << 20)),
+               taus=(65536, 1 << 20), device_gen=True),
 }
 
 
