@@ -68,6 +68,15 @@ def _lib():
                                              _i64, _I64P, _F64P, _F64P]),
                 "orc_pcdm_run": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64,
                                         _i64, _u64, _i64, _i64, _F64P, _F64P]),
+                "orc_draw_independent": (ctypes.c_int, [_u64, _u64, _i64, _i64, _I64P]),
+                "orc_draw_binomial": (ctypes.c_int, [_u64, _u64, _i64, _i64, _f64, _I64P]),
+                "orc_sample_set": (_i64, [ctypes.c_int, _f64, _u64, _u64, _i64, _i64, ctypes.c_void_p,
+                                          _i64, _I64P]),
+                "orc_independent_moments": (None, [_i64, _i64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
+                "orc_beta_du": (_f64, [_i64, _i64, _f64, _f64]),
+                "orc_pcdm_run_sampling": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64,
+                                                 _i64, _u64, _i64, _i64, ctypes.c_int, _f64,
+                                                 ctypes.c_void_p, _i64, _F64P, _F64P]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(lib, name)
@@ -117,6 +126,69 @@ def sample_nice(seed: int, k: int, tau: int, n: int) -> np.ndarray:
     if _lib().orc_sample_nice(seed & (2**64 - 1), int(k), int(tau), int(n), out) != 0:
         raise ValueError("bad sampler arguments")
     return out[: int(tau)]
+
+
+SAMPLINGS = {"nice": 0, "independent": 1, "binomial": 2}
+
+
+def draw_independent(seed: int, k: int, tau: int, n: int) -> np.ndarray:
+    """Raw picks of the tau processors of the tau-independent sampling at step
+    k, slot order, duplicates kept (section Block Samplings, independent
+    sampling)."""
+    out = np.empty(max(int(tau), 1), dtype=np.int64)
+    if _lib().orc_draw_independent(seed & (2**64 - 1), int(k), int(tau), int(n), out) != 0:
+        raise ValueError("bad sampler arguments")
+    return out[: int(tau)]
+
+
+def draw_binomial(seed: int, k: int, tau: int, n: int, pb: float) -> np.ndarray:
+    """Slot blocks of the (tau, p_b)-binomial sampling at step k: pi_k(j) of the
+    tau-nice sampler, or -1 where slot j is unavailable (implicit selection)."""
+    out = np.empty(max(int(tau), 1), dtype=np.int64)
+    if _lib().orc_draw_binomial(seed & (2**64 - 1), int(k), int(tau), int(n), float(pb), out) != 0:
+        raise ValueError("bad sampler arguments")
+    return out[: int(tau)]
+
+
+def _mask_arg(mask):
+    if mask is None:
+        return None, 0, None
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    return m.ctypes.data_as(ctypes.c_void_p), int(m.size), m
+
+
+def sample_set(sampling: str, seed: int, k: int, tau: int, n: int, pb: float = 1.0, mask=None) -> np.ndarray:
+    """S_k of a sampling with the drop mask applied, ascending, no duplicates."""
+    out = np.empty(max(int(tau), 1), dtype=np.int64)
+    mp, ml, _keep = _mask_arg(mask)
+    c = _lib().orc_sample_set(SAMPLINGS[sampling], float(pb), seed & (2**64 - 1), int(k), int(tau), int(n),
+                              mp, ml, out)
+    if c < 0:
+        raise ValueError("bad sampler arguments")
+    return out[:c].copy()
+
+
+def independent_moments(tau: int, n: int):
+    """(E|S|, E|S|^2) of the tau-independent sampling (inclusion-exclusion)."""
+    e1, e2 = _f64(), _f64()
+    _lib().orc_independent_moments(int(tau), int(n), ctypes.byref(e1), ctypes.byref(e2))
+    return e1.value, e2.value
+
+
+def beta_du(omega: int, n: int, e1: float, e2: float) -> float:
+    """beta of a doubly uniform sampling with E|S| = e1, E|S|^2 = e2 (Table ESO)."""
+    return _lib().orc_beta_du(int(omega), int(n), float(e1), float(e2))
+
+
+def beta_for(sampling: str, omega: int, tau: int, n: int, pb: float = 1.0) -> float:
+    """The ESO beta (w = L) of the named sampling."""
+    if sampling == "nice":
+        return beta_nice(omega, tau, n)
+    if sampling == "independent":
+        return beta_du(omega, n, *independent_moments(tau, n))
+    if sampling == "binomial":
+        return beta_binomial(omega, tau, n, pb)
+    raise ValueError(sampling)
 
 
 # --------------------------------------------------------------------------- #
@@ -178,10 +250,13 @@ def dual_gap(A, b, x, lam, r=None):
 class Solver:
     """Serial float64 PCDM1 state: x, r = A x - b, step counter k.
 
-    ``beta_rule``: 'nice' (tau-nice beta) or 'uniform' (min(omega, tau)).
+    ``beta_rule``: 'nice' (the sampling's own ESO beta) or 'uniform'
+    (min(omega, tau)).  ``sampling``: 'nice', 'independent' or 'binomial'
+    (with availability ``pb``); ``mask``: optional drop mask over slots.
     """
 
-    def __init__(self, A, b, lam, tau, seed=0, beta_rule="nice", beta=None, x0=None):
+    def __init__(self, A, b, lam, tau, seed=0, beta_rule="nice", beta=None, x0=None,
+                 sampling="nice", pb=1.0, mask=None):
         self.A = A
         self.m, self.n = A.m, A.n
         self.cp, self.ri, self.v = _arrays(A)
@@ -192,10 +267,13 @@ class Solver:
         self.L = np.empty(self.n)
         _lib().orc_lipschitz(self.n, self.cp, self.v, self.L)
         self.omega = int(_lib().orc_omega(self.m, self.n, self.cp, self.ri, self.v))
+        self.sampling = sampling
+        self.pb = float(pb)
+        self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         if beta is not None:
             self.beta = float(beta)
         elif beta_rule == "nice":
-            self.beta = beta_nice(self.omega, self.tau, self.n)
+            self.beta = beta_for(sampling, self.omega, self.tau, self.n, self.pb)
         elif beta_rule == "uniform":
             self.beta = beta_uniform(self.omega, self.tau)
         else:
@@ -210,9 +288,16 @@ class Solver:
         _lib().orc_residual(self.m, self.n, self.cp, self.ri, self.v, self.x, self.b, self.r)
 
     def step(self, nsteps: int = 1) -> int:
-        c = _lib().orc_pcdm_run(self.m, self.n, self.cp, self.ri, self.v, self.L, self.lam,
-                                self.beta, self.tau, self.seed & (2**64 - 1), self.k, int(nsteps),
-                                self.x, self.r)
+        if self.sampling == "nice" and self.mask is None:
+            c = _lib().orc_pcdm_run(self.m, self.n, self.cp, self.ri, self.v, self.L, self.lam,
+                                    self.beta, self.tau, self.seed & (2**64 - 1), self.k, int(nsteps),
+                                    self.x, self.r)
+        else:
+            mp, ml, _keep = _mask_arg(self.mask)
+            c = _lib().orc_pcdm_run_sampling(self.m, self.n, self.cp, self.ri, self.v, self.L, self.lam,
+                                             self.beta, self.tau, self.seed & (2**64 - 1), self.k,
+                                             int(nsteps), SAMPLINGS[self.sampling], self.pb, mp, ml,
+                                             self.x, self.r)
         if c < 0:
             raise RuntimeError("oracle step failed")
         self.k += int(nsteps)

@@ -21,6 +21,10 @@
  *     (eqs. h(x) and H_{beta,w}); for Omega = lambda*|.| and blocks of size 1
  *     the block minimiser is a soft threshold (derivation in the function).
  *   - every i in S_k is updated from the same x_k (Step 4 "in parallel").
+ *   - the tau-independent and (tau, p_b)-binomial samplings: section "Block
+ *     Samplings" (items "independent sampling", "binomial sampling", implicit
+ *     selection); their beta: Table "ESO" (doubly uniform and binomial rows),
+ *     theorem "ESO for doubly uniform samplings".
  *   - the dual bound for the duality gap is standard LASSO duality.
  *
  * Numerics: float64, round to nearest, sums in ascending index order, no
@@ -115,6 +119,12 @@ void orc_lipschitz(int64_t n, const int64_t *col_ptr, const double *val, double 
 /*   n = 6) four rounds give a subset law measurably far from uniform.       */
 /* ------------------------------------------------------------------------ */
 
+static int orc_cmp_i64_fwd(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
 static uint64_t orc_mix64(uint64_t z)
 {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -174,6 +184,135 @@ int orc_sample_nice(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int64_t *
         out[j] = (int64_t)y;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Other doubly uniform samplings (section "Block Samplings": the           */
+/* tau-independent and (tau, p_b)-binomial samplings) and their beta        */
+/* (Table ESO, doubly uniform row; theorem "ESO for doubly uniform          */
+/* samplings").                                                              */
+/*                                                                           */
+/* Concrete draws (written independently on the GPU side):                  */
+/*   * kappa_k = SplitMix64 output number k of the stream started at        */
+/*     seed XOR C, with C = 0x5043444D494E4450 for independent picks and    */
+/*     C = 0x5043444D42494E4F for binomial availability draws;               */
+/*   * u_j = SplitMix64 output number j of the stream started at kappa_k.   */
+/*   * tau-independent: processor j (j < tau) picks block                   */
+/*     floor(u_j * n / 2^64) (Lemire's multiply-shift reduction, 2019);     */
+/*     S_k is the set of distinct picks (a block picked twice is updated    */
+/*     once: the other processors idle).                                     */
+/*   * (tau, p_b)-binomial, implicit selection: slot j holds pi_k(j) of the */
+/*     tau-nice sampler and is available iff (u_j >> 11) * 2^-53 < p_b.     */
+/*     S_k is the set of available slots' blocks.                            */
+/* A drop mask models processors that are down: slot j (j < mask_len) with  */
+/* mask[j] == 0 contributes nothing, under every sampling.                  */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t orc_draw(uint64_t seed, uint64_t stream_const, uint64_t k, uint64_t j)
+{
+    uint64_t kappa = orc_splitmix64(seed ^ stream_const, k);
+    return orc_splitmix64(kappa, j);
+}
+
+/* Raw picks of the tau processors of step k (slot order, duplicates kept). */
+int orc_draw_independent(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int64_t *out)
+{
+    if (n < 1 || n > 2147483647LL || tau < 0 || tau > n)
+        return -1;
+    for (int64_t j = 0; j < tau; ++j) {
+        uint64_t u = orc_draw(seed, 0x5043444D494E4450ULL, k, (uint64_t)j);
+        out[j] = (int64_t)(((unsigned __int128)u * (uint64_t)n) >> 64);
+    }
+    return 0;
+}
+
+/* Slot j's block for the binomial sampling, or -1 when the slot is not
+ * available at step k. */
+int orc_draw_binomial(uint64_t seed, uint64_t k, int64_t tau, int64_t n, double pb, int64_t *out)
+{
+    if (orc_sample_nice(seed, k, tau, n, out) != 0 || !(pb > 0.0 && pb <= 1.0))
+        return -1;
+    for (int64_t j = 0; j < tau; ++j) {
+        uint64_t u = orc_draw(seed, 0x5043444D42494E4FULL, k, (uint64_t)j);
+        if (!((double)(u >> 11) * 0x1.0p-53 < pb))
+            out[j] = -1;
+    }
+    return 0;
+}
+
+/*
+ * S_k of the given sampling (0 = tau-nice, 1 = tau-independent,
+ * 2 = (tau, p_b)-binomial) with the drop mask applied, written to out in
+ * ascending order without duplicates.  Returns |S_k|, or -1 for bad
+ * arguments.  out needs room for tau entries.
+ */
+int64_t orc_sample_set(int sampling, double pb, uint64_t seed, uint64_t k, int64_t tau, int64_t n,
+                       const uint8_t *mask, int64_t mask_len, int64_t *out)
+{
+    int rc;
+    int64_t cnt = 0;
+    if (sampling == 0)
+        rc = orc_sample_nice(seed, k, tau, n, out);
+    else if (sampling == 1)
+        rc = orc_draw_independent(seed, k, tau, n, out);
+    else if (sampling == 2)
+        rc = orc_draw_binomial(seed, k, tau, n, pb, out);
+    else
+        return -1;
+    if (rc != 0)
+        return -1;
+    for (int64_t j = 0; j < tau; ++j) {
+        if (out[j] < 0 || (mask && j < mask_len && mask[j] == 0))
+            continue;
+        out[cnt++] = out[j];
+    }
+    qsort(out, (size_t)cnt, sizeof(int64_t), orc_cmp_i64_fwd);
+    {
+        int64_t u = 0;
+        for (int64_t t = 0; t < cnt; ++t)
+            if (t == 0 || out[t] != out[t - 1])
+                out[u++] = out[t];
+        cnt = u;
+    }
+    return cnt;
+}
+
+/*
+ * First two moments of |S| for the tau-independent sampling.  Block i is
+ * missed by all tau processors with probability (1 - 1/n)^tau, and blocks
+ * i != j both by all with probability (1 - 2/n)^tau, so by inclusion and
+ * exclusion
+ *     E|S|   = n (1 - (1-1/n)^tau),
+ *     E|S|^2 = E|S| + n(n-1) (1 - 2(1-1/n)^tau + (1-2/n)^tau).
+ * The last bracket cancels badly when tau << n; it is evaluated as
+ * (1-a)^2 - (a^2 - c) with a = (1-1/n)^tau, c = (1-2/n)^tau and
+ * a^2 - c = c ((1 + 1/(n(n-2)))^tau - 1), using log1p / expm1.
+ */
+void orc_independent_moments(int64_t tau, int64_t n, double *e1, double *e2)
+{
+    double nn = (double)n, t = (double)tau, one_minus_a, pair;
+    if (n == 1) {
+        *e1 = 1.0;
+        *e2 = 1.0;
+        return;
+    }
+    one_minus_a = -expm1(t * log1p(-1.0 / nn));
+    if (n == 2) {
+        pair = 1.0 - 2.0 * pow(0.5, t);
+    } else {
+        double c = exp(t * log1p(-2.0 / nn));
+        pair = one_minus_a * one_minus_a - c * expm1(t * log1p(1.0 / (nn * (nn - 2.0))));
+    }
+    *e1 = nn * one_minus_a;
+    *e2 = *e1 + nn * (nn - 1.0) * pair;
+}
+
+/* Doubly uniform sampling with moments E|S| = e1, E|S|^2 = e2:
+ * beta = 1 + (omega-1)(e2/e1 - 1)/max(1, n-1), w = L. */
+double orc_beta_du(int64_t omega, int64_t n, double e1, double e2)
+{
+    double den = (n - 1 > 1) ? (double)(n - 1) : 1.0;
+    return 1.0 + (double)(omega - 1) * (e2 / e1 - 1.0) / den;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -347,6 +486,37 @@ int64_t orc_pcdm_run(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t
             return -1;
         }
         c = orc_step_with_set(m, n, col_ptr, row_idx, val, L, lambda, beta, tau, S, x, r);
+        if (c < 0) {
+            free(S);
+            return -1;
+        }
+        total += c;
+    }
+    free(S);
+    return total;
+}
+
+/*
+ * As orc_pcdm_run, with S_k drawn by orc_sample_set (sampling, p_b, drop
+ * mask).  beta is the caller's.
+ */
+int64_t orc_pcdm_run_sampling(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                              const double *val, const double *L, double lambda, double beta,
+                              int64_t tau, uint64_t seed, int64_t k0, int64_t nsteps, int sampling,
+                              double pb, const uint8_t *mask, int64_t mask_len, double *x, double *r)
+{
+    int64_t *S = (int64_t *)malloc((size_t)(tau > 0 ? tau : 1) * sizeof(int64_t));
+    int64_t total = 0;
+    if (!S)
+        return -1;
+    for (int64_t k = k0; k < k0 + nsteps; ++k) {
+        int64_t cnt = orc_sample_set(sampling, pb, seed, (uint64_t)k, tau, n, mask, mask_len, S);
+        int64_t c;
+        if (cnt < 0) {
+            free(S);
+            return -1;
+        }
+        c = orc_step_with_set(m, n, col_ptr, row_idx, val, L, lambda, beta, cnt, S, x, r);
         if (c < 0) {
             free(S);
             return -1;
