@@ -98,6 +98,11 @@ typedef struct pcdm_info {
                              /* 2 = explicit value set with option "beta"         */
     int32_t lanes_per_column;/* step-kernel schedule: lanes reading one column    */
     int32_t chunks_per_lane; /* ... and 4-entry chunks each lane holds          */
+    int32_t sampling;        /* 0 = tau-nice, 1 = tau-independent, 2 = binomial   */
+    int32_t reserved0;
+    double binomial_p;       /* availability p_b of a binomial slot               */
+    double expected_set_size;/* E|S_k| of the sampling (drop mask not included)   */
+    int64_t mask_len;        /* slots covered by the drop mask (0 = none)         */
 } pcdm_info;
 
 /*
@@ -106,7 +111,7 @@ typedef struct pcdm_info {
  *   b       : [m] float64, host or device as A->on_device says;
  *   lambda  : >= 0 and finite;
  *   tau     : sampled coordinates per step, 1 <= tau <= n;
- *   seed    : key of the tau-nice sampler (S_k depends on (seed, k) only).
+ *   seed    : key of the sampler (S_k depends on (seed, k) and the sampling only).
  * Requires 1 <= n <= 2^31 - 2 and 1 <= m with the working residual under
  * 4 GiB (m < 2^30 for PCDM_F32/PCDM_BF16, m < 2^29 for PCDM_F64).  Rejects (PCDM_EINVAL) empty or all-zero
  * columns (the paper assumes L_i > 0), repeated rows in a column, rows out
@@ -127,7 +132,27 @@ const char *pcdm_last_error(void);
  * Set a numeric option.  Keys:
  *   "refresh_every"    steps between float64 refreshes r = A x - b (default
  *                      ceil(n/tau), one epoch; 0 disables);
- *   "beta_rule"        0 = tau-nice beta (default), 1 = min(omega, tau);
+ *   "beta_rule"        0 = the ESO beta of the sampling in use (default):
+ *                      tau-nice 1 + (omega-1)(tau-1)/max(1,n-1); binomial
+ *                      1 + p_b(omega-1)(tau-1)/max(1,n-1); tau-independent
+ *                      the doubly uniform 1 + (omega-1)(E|S|^2/E|S| - 1)/max(1,n-1)
+ *                      (Table "ESO"; theorem "ESO for doubly uniform
+ *                      samplings"); 1 = min(omega, tau);
+ *   "sampling"         0 = tau-nice (default); 1 = tau-independent: each of
+ *                      tau processors picks a block uniformly and
+ *                      independently, a block picked twice is updated once
+ *                      (section "Block Samplings", independent sampling; the
+ *                      sampler of the paper's own LASSO runs; needs 4n bytes
+ *                      of claim stamps, allocated on first use); 2 =
+ *                      (tau, p_b)-binomial with implicit selection: slot j of
+ *                      the tau-nice S_k updates its block only when available,
+ *                      with probability p_b (binomial sampling, case 2).
+ *                      Draws: kappa_k = SplitMix64 output k from seed ^
+ *                      0x5043444D494E4450 (independent) or seed ^
+ *                      0x5043444D42494E4F (binomial); u_j = output j from
+ *                      kappa_k; a pick is floor(u_j n / 2^64); a slot is
+ *                      available iff (u_j >> 11) 2^-53 < p_b;
+ *   "binomial_p"       p_b in (0, 1] (default 1);
  *   "beta"             explicit beta > 0 (sets beta_rule 2);
  *   "lambda"           new lambda >= 0;
  *   "tau"              new tau in [1, n] (beta recomputed by the rule);
@@ -231,6 +256,30 @@ int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream);
  */
 int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device,
                 void *stream);
+
+/*
+ * The draws of any sampling (section "Block Samplings"; draws as under
+ * option "sampling"): out_device[j] (int32, device memory, tau entries) is
+ * slot j's block at step k with key seed: pi_k(j) for tau-nice; the raw pick
+ * of processor j for tau-independent (duplicates kept: pcdm_step updates each
+ * distinct pick once); pi_k(j), or -1 when the slot is unavailable, for
+ * binomial.  No drop mask.  Asynchronous.
+ */
+int pcdm_sample_draw(int32_t sampling, double binomial_p, uint64_t seed, uint64_t k, int64_t tau,
+                     int64_t n, int32_t *out_device, void *stream);
+
+/*
+ * Drop mask (fault model: processors that are down; binomial sampling's
+ * "unreliable processors" made deterministic).  mask[j] == 0 removes slot j
+ * (j < len) from every following step under every sampling: the slot
+ * computes nothing and scatters nothing; slots >= len are alive.  beta is
+ * not changed (the sampling's beta stays valid: dropping slots of a tau-nice
+ * sample leaves a smaller nice sample, whose beta is smaller).  len = 0
+ * (mask may be NULL) removes the mask.  0 <= len <= n; mask is host or
+ * device memory as on_device says and is copied.  Synchronous.
+ */
+int pcdm_set_slot_mask(pcdm_problem *h, const uint8_t *mask, int64_t len, int32_t on_device,
+                       void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched solver: many independent LASSO problems (uneven m_j, n_j, a

@@ -8,4 +8,4 @@ not been built.
 
 from ._lib import (EXPORTS, LIB_PATH, PCDM_BF16, PCDM_F32, PCDM_F64, PCDMError,  # noqa: F401
                    load)
-from .api import Batch, Problem, current_stream, sample  # noqa: F401
+from .api import Batch, Problem, current_stream, sample, sample_draw  # noqa: F401

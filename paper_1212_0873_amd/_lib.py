@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "PCDM_OK", -1: "PCDM_EINVAL", -2: "PCDM_ENOMEM", -3: "PCDM_ED
 EXPORTS = ("pcdm_create", "pcdm_destroy", "pcdm_last_error", "pcdm_set_option", "pcdm_get_info",
            "pcdm_step", "pcdm_objective", "pcdm_get_x", "pcdm_set_x", "pcdm_get_residual",
            "pcdm_grad_backward", "pcdm_set_rhs", "pcdm_kernel_time", "pcdm_autotune", "pcdm_sample",
+           "pcdm_sample_draw", "pcdm_set_slot_mask",
            "pcdm_batch_create", "pcdm_batch_step", "pcdm_batch_objective", "pcdm_batch_set_active",
            "pcdm_batch_get_x", "pcdm_batch_get_info", "pcdm_batch_set_option", "pcdm_batch_autotune",
            "pcdm_batch_destroy")
@@ -35,7 +36,9 @@ class pcdm_info(ctypes.Structure):
                 ("refresh_every", ctypes.c_int64), ("nonzero_updates", ctypes.c_int64),
                 ("stored_nnz", ctypes.c_int64), ("beta", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("atb_inf", ctypes.c_double), ("dtype", ctypes.c_int32), ("beta_rule", ctypes.c_int32),
-                ("lanes_per_column", ctypes.c_int32), ("chunks_per_lane", ctypes.c_int32)]
+                ("lanes_per_column", ctypes.c_int32), ("chunks_per_lane", ctypes.c_int32),
+                ("sampling", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("binomial_p", ctypes.c_double),
+                ("expected_set_size", ctypes.c_double), ("mask_len", ctypes.c_int64)]
 
 
 class PCDMError(RuntimeError):
@@ -72,6 +75,8 @@ def load() -> ctypes.CDLL:
             "pcdm_get_residual": [vp, vp, i32, vp],
             "pcdm_grad_backward": [vp, vp, vp, pd, i32, vp],
             "pcdm_sample": [u64, u64, i64, i64, vp, vp],
+            "pcdm_sample_draw": [i32, f64, u64, u64, i64, i64, vp, vp],
+            "pcdm_set_slot_mask": [vp, vp, i64, i32, vp],
             "pcdm_kernel_time": [vp, ctypes.c_char_p, ctypes.POINTER(i64), pd],
             "pcdm_set_rhs": [vp, vp, i32, vp],
             "pcdm_autotune": [vp, i64, vp],

@@ -112,6 +112,22 @@ class Problem:
     def set_option(self, key: str, value: float) -> None:
         check(self._lib.pcdm_set_option(self._h, key.encode(), float(value)))
 
+    def set_sampling(self, sampling: str, pb: float = 1.0) -> None:
+        """'nice', 'independent' or 'binomial' (availability pb); beta follows
+        the sampling unless an explicit beta was set."""
+        if sampling == "binomial":
+            self.set_option("binomial_p", pb)
+        self.set_option("sampling", SAMPLINGS[sampling])
+
+    def set_slot_mask(self, mask) -> None:
+        """Drop mask over slots (0 = processor down); None removes it."""
+        if mask is None:
+            check(self._lib.pcdm_set_slot_mask(self._h, None, 0, 0, current_stream()))
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        check(self._lib.pcdm_set_slot_mask(self._h, m.ctypes.data_as(ctypes.c_void_p), int(m.size), 0,
+                                           current_stream()))
+
     def info(self) -> dict:
         inf = pcdm_info()
         check(self._lib.pcdm_get_info(self._h, ctypes.byref(inf)))
@@ -217,6 +233,20 @@ def sample(seed: int, k: int, tau: int, n: int):
     out = torch.empty(max(int(tau), 1), dtype=torch.int32, device="cuda")
     check(load().pcdm_sample(int(seed) & (2**64 - 1), int(k), int(tau), int(n), out.data_ptr(),
                              current_stream()))
+    return out[: int(tau)]
+
+
+SAMPLINGS = {"nice": 0, "independent": 1, "binomial": 2}
+
+
+def sample_draw(sampling: str, seed: int, k: int, tau: int, n: int, pb: float = 1.0):
+    """Slot draws of a sampling as an int32 CUDA tensor: the tau-nice block, the
+    raw independent pick (duplicates kept), or the binomial slot's block / -1
+    when unavailable."""
+    torch = _torch()
+    out = torch.empty(max(int(tau), 1), dtype=torch.int32, device="cuda")
+    check(load().pcdm_sample_draw(SAMPLINGS[sampling], float(pb), int(seed) & (2**64 - 1), int(k), int(tau),
+                                  int(n), out.data_ptr(), current_stream()))
     return out[: int(tau)]
 
 

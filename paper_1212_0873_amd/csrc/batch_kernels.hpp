@@ -45,9 +45,10 @@ k_batch_gather(char *__restrict__ seg, const BatchInst *__restrict__ desc, const
             continue;
         const BatchInst d = desc[j];
         const NiceKey key = nice_key_wave(d.seed, d.k, (uint32_t)d.n);
+        const SlotDraw sd = slot_draw_for(plan_nice(), d.seed, d.k);
         gather_tile<V, G, C>(seg + d.rec_base, d.lay, r + d.row_base, xm + d.col_base, id_slot + d.slot_base,
-                             delta_slot + d.slot_base, key, tl, (t - d.step_tile0) * 64, d.tau, d.inv_beta, d.lam,
-                             nz);
+                             delta_slot + d.slot_base, key, sd, tl, (t - d.step_tile0) * 64, d.tau, d.inv_beta,
+                             d.lam, nz);
     }
     const uint64_t tot = block_sum_u64(nz, s_red);
     if (threadIdx.x == 0 && tot)

@@ -547,6 +547,9 @@ int pcdm_batch_get_info(pcdm_batch *B, int index, pcdm_info *out)
     out->stored_nnz = B->stored[index];
     out->beta = B->beta[index];
     out->lambda = B->lambda[index];
+    out->sampling = 0;  // batches use the tau-nice sampler
+    out->binomial_p = 1.0;
+    out->expected_set_size = (double)d.tau;
     out->atb_inf = B->atb_inf[index];
     out->dtype = B->dtype;
     out->lanes_per_column = B->lanes;

@@ -267,18 +267,20 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
                                             const typename ValT<V>::T *__restrict__ r, double *__restrict__ xm,
                                             int32_t *__restrict__ id_slot,
                                             typename ValT<V>::T *__restrict__ delta_slot, const NiceKey &key,
-                                            const TileLanes<G> &tl, int64_t base, int64_t tau, double inv_beta,
-                                            double lam, uint64_t &nz)
+                                            const SlotDraw &sd, const TileLanes<G> &tl, int64_t base, int64_t tau,
+                                            double inv_beta, double lam, uint64_t &nz)
 {
     using T = typename ValT<V>::T;
     const int64_t slot = base + tl.lane;
     const bool act = slot < tau;
+    bool live = false;
     uint32_t i = 0;
     int64_t off = 0;
     int32_t dp = 0;
     double xi = 0.0, il = 0.0;
-    if (act) {
-        i = nice_slot((uint32_t)slot, key);
+    if (act)
+        live = draw_slot(sd, key, (uint32_t)slot, i);
+    if (live) {
         locate<V>(lay, i, off, dp);
         const double *hdr = reinterpret_cast<const double *>(seg + off);
         xi = hdr[0];
@@ -351,7 +353,7 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
     if (act) {
         const double scale = il * inv_beta;  // 1 / (beta L_i)
         const double xn = soft_threshold<double>(xi - (double)mine * scale, lam * scale);
-        const double d = xn - xi;
+        const double d = live ? xn - xi : 0.0;
         id_slot[slot] = (int32_t)i;
         delta_slot[slot] = (T)d;
         if (d != 0.0) {
@@ -392,15 +394,17 @@ __global__ void __launch_bounds__(kBlock)
 k_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
          double *__restrict__ xm, int32_t *__restrict__ id_slot, typename ValT<V>::T *__restrict__ delta_slot,
          const Ctrl *__restrict__ ctrl, uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau,
-         uint32_t n, double inv_beta, double lam)
+         uint32_t n, double inv_beta, double lam, SlotPlan plan)
 {
     __shared__ uint32_t s_keys[kNiceRounds];
     __shared__ uint64_t s_red[kBlock / 64];
-    const NiceKey key = nice_key_block(seed, ctrl->k, n, s_keys);
+    const uint64_t k = ctrl->k;
+    const NiceKey key = nice_key_block(seed, k, n, s_keys);
+    const SlotDraw sd = slot_draw_for(plan, seed, k);
     const TileLanes<G> tl;
     uint64_t nz = 0;
     for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64)
-        gather_tile<V, G, C>(seg, lay, r, xm, id_slot, delta_slot, key, tl, base, tau, inv_beta, lam, nz);
+        gather_tile<V, G, C>(seg, lay, r, xm, id_slot, delta_slot, key, sd, tl, base, tau, inv_beta, lam, nz);
     const uint64_t tot = block_sum_u64(nz, s_red);
     if (threadIdx.x == 0 && tot)
         nz_part[blockIdx.x] += tot;
@@ -424,12 +428,19 @@ k_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restr
 
 // The sampler alone (for tests and callers that want S_k).
 __global__ void __launch_bounds__(kBlock)
-k_sample(uint64_t seed, uint64_t step, int64_t tau, uint32_t n, int32_t *__restrict__ out)
+k_sample(uint64_t seed, uint64_t step, int64_t tau, uint32_t n, int mode, double pb, int32_t *__restrict__ out)
 {
     __shared__ uint32_t s_keys[kNiceRounds];
     const NiceKey key = nice_key_block(seed, step, n, s_keys);
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < tau; j += (int64_t)gridDim.x * kBlock)
-        out[j] = (int32_t)nice_slot((uint32_t)j, key);
+    SlotPlan plan = plan_nice();
+    plan.mode = mode;
+    plan.pb = pb;
+    const SlotDraw sd = slot_draw_for(plan, seed, step);
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < tau; j += (int64_t)gridDim.x * kBlock) {
+        uint32_t i = 0;
+        const bool avail = slot_block(sd, key, (uint32_t)j, i);
+        out[j] = avail ? (int32_t)i : -1;
+    }
 }
 
 // --------------------------------------------------------------------------

@@ -116,6 +116,14 @@ struct pcdm_problem {
     int timing = 0;
     KernelClock clocks[CLK_COUNT];
 
+    // sampling of S_k (kSampleNice / kSampleIndependent / kSampleBinomial)
+    int sampling = kSampleNice;
+    double pb = 1.0;
+    uint8_t *mask = nullptr;   // device drop mask over slots, or nullptr
+    int64_t mask_len = 0;
+    uint32_t *claim = nullptr; // [n] claim stamps for independent picks
+    int64_t claim_base = 0;    // step at which claim was last zeroed
+
     // adjoint solve settings
     double adj_tol = 1e-6;
     int64_t adj_max_epochs = 20000;
@@ -140,21 +148,99 @@ void free_problem(pcdm_problem *P)
     for (hipEvent_t e : P->event_pool)
         (void)hipEventDestroy(e);
     void *bufs[] = {P->seg, P->pc, P->x, P->r, P->r64, P->b64, P->id_slot,
-                    P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2};
+                    P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
     delete P;
 }
 
+// tau-independent picks: with p1 = P(i in S) and p2 = P(i, j in S) for i != j,
+// E|S| = n p1 and E|S|^2/E|S| - 1 = (n-1) p2 / p1.  p2 = 1 - 2(1-1/n)^tau +
+// (1-2/n)^tau is summed as the binomial series
+//     p2 = sum_{s>=2} (-1)^s C(tau, s) (2^s - 2) / n^s,
+// whose terms shrink from s = 2 on (tau <= n), so it keeps full relative
+// precision where the closed form cancels (tau << n).
+void independent_moments(int64_t tau, int64_t n, double &e1, double &ratio)
+{
+    const double nn = (double)n, t = (double)tau;
+    const double p1 = -std::expm1(t * std::log1p(-1.0 / nn));
+    e1 = nn * p1;
+    ratio = 0.0;
+    if (n < 2 || tau < 2)
+        return;
+    double c = 1.0, pw = 1.0, p2 = 0.0;  // c = C(tau, s) / n^s, pw = 2^s
+    for (int64_t q = 1; q <= tau && q <= 4096; ++q) {
+        c *= (t - (double)(q - 1)) / ((double)q * nn);
+        pw *= 2.0;
+        if (q < 2)
+            continue;
+        const double term = c * (pw - 2.0);
+        p2 += (q & 1) ? -term : term;
+        if (term <= 1e-18 * std::fabs(p2))
+            break;
+    }
+    ratio = (nn - 1.0) * p2 / p1;
+}
+
+// E|S| of the sampling (before any drop mask).
+double expected_set_size(const pcdm_problem *P)
+{
+    if (P->sampling == kSampleIndependent) {
+        double e1, ratio;
+        independent_moments(P->tau, P->n, e1, ratio);
+        return e1;
+    }
+    if (P->sampling == kSampleBinomial)
+        return (double)P->tau * P->pb;
+    return (double)P->tau;
+}
+
+// beta_rule 0: the ESO beta of the sampling in use (Table ESO: tau-nice row;
+// doubly uniform row beta = 1 + (omega-1)(E|S|^2/E|S| - 1)/max(1, n-1) for
+// tau-independent picks; binomial row).  beta_rule 1: min(omega, tau).
 int compute_beta(pcdm_problem *P)
 {
     const double om = (double)P->omega, ta = (double)P->tau, nn = (double)P->n;
-    if (P->beta_rule == 0)
-        P->beta = 1.0 + (om - 1.0) * (ta - 1.0) / std::max(1.0, nn - 1.0);
-    else if (P->beta_rule == 1)
+    const double den = std::max(1.0, nn - 1.0);
+    if (P->beta_rule == 0) {
+        if (P->sampling == kSampleIndependent) {
+            double e1, ratio;
+            independent_moments(P->tau, P->n, e1, ratio);
+            P->beta = 1.0 + (om - 1.0) * ratio / den;
+        } else if (P->sampling == kSampleBinomial) {
+            P->beta = 1.0 + P->pb * (om - 1.0) * (ta - 1.0) / den;
+        } else {
+            P->beta = 1.0 + (om - 1.0) * (ta - 1.0) / den;
+        }
+    } else if (P->beta_rule == 1) {
         P->beta = std::min(om, ta);
+    }
     return PCDM_OK;
+}
+
+// Kernel view of the sampling.
+SlotPlan slot_plan(const pcdm_problem *P)
+{
+    SlotPlan p = plan_nice();
+    p.mode = P->sampling;
+    p.pb = P->pb;
+    p.mask = P->mask;
+    p.mask_len = P->mask_len;
+    p.claim = P->claim;
+    p.claim_base = (uint64_t)P->claim_base;
+    return p;
+}
+
+// Zero the claim stamps and restart their numbering at step k (a fill
+// kernel, so the call is safe inside a captured stream).
+void reset_claims(pcdm_problem *P, int64_t k, hipStream_t s)
+{
+    if (!P->claim)
+        return;
+    const int g = grid_for(P->n, kBlock, P->nblk_max);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(g), dim3(kBlock), 0, s, P->claim, 0u, P->n);
+    P->claim_base = k;
 }
 
 // Tile schedule from the mean padded column length: G lanes per column with
@@ -273,7 +359,7 @@ template <typename V> struct Ops {
         hipEvent_t t0 = clock_start(P, s);
         hipLaunchKernelGGL((k_gather<V, G, C>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
                            (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part,
-                           P->seed, P->tau, (uint32_t)P->n, 1.0 / P->beta, P->lambda);
+                           P->seed, P->tau, (uint32_t)P->n, 1.0 / P->beta, P->lambda, slot_plan(P));
         clock_stop(P, CLK_GATHER, t0, s);
         hipEvent_t t1 = clock_start(P, s);
         hipLaunchKernelGGL((k_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
@@ -700,6 +786,22 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             h->chunks = c;
             h->lanes_auto = 0;
         }
+    } else if (k == "sampling") {
+        const int v = (int)value;
+        if ((double)v != value || v < kSampleNice || v > kSampleBinomial)
+            return fail(PCDM_EINVAL, "sampling must be 0 (tau-nice), 1 (tau-independent) or 2 (binomial)");
+        if (v == kSampleIndependent && !h->claim) {
+            HIP_TRY(hipMalloc(&h->claim, (size_t)h->n * sizeof(uint32_t)));
+            reset_claims(h, h->k_host, h->last_stream);
+            PCDM_TRY(check_launch("claim reset"));
+        }
+        h->sampling = v;
+        compute_beta(h);
+    } else if (k == "binomial_p") {
+        if (!(value > 0.0 && value <= 1.0))
+            return fail(PCDM_EINVAL, "binomial_p must be in (0, 1]");
+        h->pb = value;
+        compute_beta(h);
     } else if (k == "adj_tol") {
         if (!(value > 0.0))
             return fail(PCDM_EINVAL, "adj_tol must be > 0");
@@ -760,6 +862,10 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->beta_rule = h->beta_rule;
     out->lanes_per_column = h->lanes;
     out->chunks_per_lane = h->chunks;
+    out->sampling = h->sampling;
+    out->binomial_p = h->pb;
+    out->expected_set_size = expected_set_size(h);
+    out->mask_len = h->mask_len;
     return PCDM_OK;
 }
 
@@ -772,6 +878,8 @@ int pcdm_step(pcdm_problem *h, int64_t nsteps, void *stream)
     hipStream_t s = (hipStream_t)stream;
     h->last_stream = s;
     for (int64_t q = 0; q < nsteps; ++q) {
+        if (h->claim && h->k_host - h->claim_base >= (int64_t)0xFFFFFFFE)
+            reset_claims(h, h->k_host, s);  // 32-bit stamps must not repeat
         PCDM_TRY(dispatch(h->dtype, [&](auto ops) { return decltype(ops)::step_once(h, s); }));
         h->k_host += 1;
         if (h->refresh_every > 0 && h->k_host % h->refresh_every == 0)
@@ -873,6 +981,7 @@ int pcdm_set_x(pcdm_problem *h, const void *x, int32_t dtype, int32_t on_device,
         return PCDM_OK;
     });
     hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(kBlock), 0, s, &h->ctrl->k, (uint64_t)k, (int64_t)1);
+    reset_claims(h, k, s);  // stamps of steps after k may have been used already
     int st = check_launch("pcdm_set_x");
     if (st == PCDM_OK)
         st = refresh_now(h, s);
@@ -1109,18 +1218,54 @@ int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream)
     return st;
 }
 
-int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device, void *stream)
+int pcdm_sample_draw(int32_t sampling, double binomial_p, uint64_t seed, uint64_t k, int64_t tau, int64_t n,
+                     int32_t *out_device, void *stream)
 {
     if (!out_device)
         return fail(PCDM_EINVAL, "NULL output");
     if (n < 1 || n > INT32_MAX || tau < 0 || tau > n)
         return fail(PCDM_EINVAL, "need 1 <= n <= 2^31-1 and 0 <= tau <= n");
+    if (sampling < kSampleNice || sampling > kSampleBinomial)
+        return fail(PCDM_EINVAL, "sampling must be 0, 1 or 2");
+    if (sampling == kSampleBinomial && !(binomial_p > 0.0 && binomial_p <= 1.0))
+        return fail(PCDM_EINVAL, "binomial_p must be in (0, 1]");
     if (tau == 0)
         return PCDM_OK;
     hipStream_t s = (hipStream_t)stream;
     const int g = grid_for(tau, kBlock, 4096);
-    hipLaunchKernelGGL(k_sample, dim3(g), dim3(kBlock), 0, s, seed, k, tau, (uint32_t)n, out_device);
-    return check_launch("pcdm_sample");
+    hipLaunchKernelGGL(k_sample, dim3(g), dim3(kBlock), 0, s, seed, k, tau, (uint32_t)n, (int)sampling,
+                       binomial_p, out_device);
+    return check_launch("pcdm_sample_draw");
+}
+
+int pcdm_sample(uint64_t seed, uint64_t k, int64_t tau, int64_t n, int32_t *out_device, void *stream)
+{
+    return pcdm_sample_draw(kSampleNice, 1.0, seed, k, tau, n, out_device, stream);
+}
+
+int pcdm_set_slot_mask(pcdm_problem *h, const uint8_t *mask, int64_t len, int32_t on_device, void *stream)
+{
+    if (!h)
+        return fail(PCDM_EINVAL, "NULL handle");
+    if (len < 0 || (len > 0 && !mask))
+        return fail(PCDM_EINVAL, "need len >= 0 and a mask when len > 0");
+    if (len > h->n)
+        return fail(PCDM_EINVAL, "mask longer than n (tau never exceeds n)");
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    HIP_TRY(hipStreamSynchronize(s));  // steps already queued may still read the old mask
+    if (h->mask)
+        HIP_TRY(hipFree(h->mask));
+    h->mask = nullptr;
+    h->mask_len = 0;
+    if (len == 0)
+        return PCDM_OK;
+    HIP_TRY(hipMalloc(&h->mask, (size_t)len));
+    HIP_TRY(hipMemcpyAsync(h->mask, mask, (size_t)len, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->mask_len = len;
+    return PCDM_OK;
 }
 
 }  // extern "C"

@@ -23,6 +23,19 @@
 //     network again while the value is >= n.
 // Ten rounds: fewer leave the subset law visibly non-uniform on the tiny
 // domains of small n.
+//
+// Other doubly uniform samplings (section "Block Samplings"), from the same
+// primitives.  Step key kappa_k = SplitMix64 output k of the stream started at
+// seed ^ 0x5043444D494E4450 (independent picks) or seed ^ 0x5043444D42494E4F
+// (binomial availability); draw j of step k = SplitMix64 output j of the
+// stream started at kappa_k.
+//   * tau-independent: processor j picks block floor(draw_j * n / 2^64)
+//     (Lemire's multiply-shift reduction); a block picked by several
+//     processors is updated once (the first claim at its stamp wins, the
+//     others idle), so S_k is the set of distinct picks.
+//   * (tau, p_b)-binomial, implicit selection: slot j keeps its tau-nice block
+//     pi_k(j) and is available iff (draw_j >> 11) * 2^-53 < p_b.
+// A drop mask (processors that are down) removes slot j when mask[j] == 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -120,6 +133,78 @@ __device__ __forceinline__ NiceKey nice_key_wave(uint64_t seed, uint64_t step, u
     key.mask = (1u << key.half) - 1u;
     key.n = n;
     return key;
+}
+
+enum : int { kSampleNice = 0, kSampleIndependent = 1, kSampleBinomial = 2 };
+constexpr uint64_t kIndepStream = 0x5043444D494E4450ull;
+constexpr uint64_t kBinomStream = 0x5043444D42494E4Full;
+
+// What the host fixes about a problem's sampling (kernel argument).
+struct SlotPlan {
+    int mode;                // kSample*
+    double pb;               // availability of a binomial slot
+    const uint8_t *mask;     // nullptr: every slot alive
+    int64_t mask_len;        // slots >= mask_len are alive
+    uint32_t *claim;         // [n] claim stamps (independent picks)
+    uint64_t claim_base;     // step at which claim was last zeroed
+};
+
+__host__ __device__ inline SlotPlan plan_nice()
+{
+    SlotPlan p;
+    p.mode = kSampleNice;
+    p.pb = 1.0;
+    p.mask = nullptr;
+    p.mask_len = 0;
+    p.claim = nullptr;
+    p.claim_base = 0;
+    return p;
+}
+
+// The plan specialised to step k.
+struct SlotDraw {
+    SlotPlan plan;
+    uint64_t kappa;
+    uint32_t stamp;  // unique per step since the last zeroing of claim, never 0
+};
+
+__device__ __forceinline__ SlotDraw slot_draw_for(const SlotPlan &p, uint64_t seed, uint64_t k)
+{
+    SlotDraw d;
+    d.plan = p;
+    d.kappa = 0;
+    if (p.mode == kSampleIndependent)
+        d.kappa = splitmix_output(seed ^ kIndepStream, k);
+    else if (p.mode == kSampleBinomial)
+        d.kappa = splitmix_output(seed ^ kBinomStream, k);
+    d.stamp = (uint32_t)(k - p.claim_base) + 1u;
+    return d;
+}
+
+// Slot j's block before masks and claims; false when a binomial slot is
+// unavailable.
+__device__ __forceinline__ bool slot_block(const SlotDraw &d, const NiceKey &key, uint32_t j, uint32_t &i)
+{
+    if (d.plan.mode == kSampleIndependent) {
+        i = (uint32_t)__umul64hi(splitmix_output(d.kappa, j), (uint64_t)key.n);
+        return true;
+    }
+    i = nice_slot(j, key);
+    if (d.plan.mode == kSampleBinomial)
+        return (double)(splitmix_output(d.kappa, j) >> 11) * 0x1.0p-53 < d.plan.pb;
+    return true;
+}
+
+// Slot j's block and whether the slot updates it this step (mask, binomial
+// availability, first claim of an independent pick).
+__device__ __forceinline__ bool draw_slot(const SlotDraw &d, const NiceKey &key, uint32_t j, uint32_t &i)
+{
+    bool keep = slot_block(d, key, j, i);
+    if (d.plan.mask && (int64_t)j < d.plan.mask_len && d.plan.mask[j] == 0)
+        keep = false;
+    if (keep && d.plan.mode == kSampleIndependent)
+        keep = atomicExch(d.plan.claim + i, d.stamp) != d.stamp;
+    return keep;
 }
 
 }  // namespace pcdm
