@@ -23,6 +23,7 @@ import os
 import sys
 import time
 import types
+from typing import Optional
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -180,6 +181,146 @@ def run_dtypes(args) -> int:
     return 0
 
 
+def copy_bandwidth_gbps(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Read + write bandwidth of a plain device-to-device copy (torch)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes * reps / dt / 1e9
+
+
+def gpu_clocks() -> Optional[str]:
+    """Current clock levels as rocm-smi reports them (best effort)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+    except Exception:  # noqa: BLE001 - the tool may be absent
+        return None
+    lines = [ln.strip() for ln in r.stdout.splitlines() if "clock level" in ln.lower()]
+    return "; ".join(lines) if lines else None
+
+
+def measure_rate(p, tau: int, min_seconds: float = 1.0, warmup: int = 20) -> dict:
+    """Updates/s of the current handle over at least min_seconds of steps, and
+    the average gather/scatter launch time from HIP events (a separate run, so
+    the events do not perturb the rate)."""
+    import torch
+    p.step(warmup)
+    torch.cuda.synchronize()
+    steps = 16
+    while True:
+        t0 = time.perf_counter()
+        p.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+        steps = int(steps * max(2.0, 1.2 * min_seconds / max(dt, 1e-6)))
+    p.set_option("kernel_timing", 1)
+    p.step(min(steps, 2000))
+    ng, gms = p.kernel_time("gather")
+    ns, sms = p.kernel_time("scatter")
+    p.set_option("kernel_timing", 0)
+    return {"steps": steps, "seconds": dt, "us_per_step": dt / steps * 1e6,
+            "slot_updates_per_s": tau * steps / dt,
+            "gather_avg_us": gms / max(ng, 1) * 1e3, "scatter_avg_us": sms / max(ns, 1) * 1e3}
+
+
+def run_taus(args) -> int:
+    """tau sweep on the 1e6 x 1e7 instance and its 3.33e6-row variant (omega
+    about 61): updates/s, kernel times and time to a certified 1e-6 gap per
+    tau; the fixed cost of a step (tau = 1); a plain copy's bandwidth."""
+    import numpy as np
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import make_config
+
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC, "mode": "taus", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
+           "device": torch.cuda.get_device_name(0), "copy_gbps": copy_bandwidth_gbps(),
+           "gpu_clocks": gpu_clocks(), "workloads": {}}
+    print(f"[bench] copy {out['copy_gbps']:.0f} GB/s", file=sys.stderr, flush=True)
+    for cfg in ("lasso_1e6x1e7", "lasso_3.33e6x1e7"):
+        inst = make_config(cfg, dtype=args.dtype)
+        A = inst.A
+        d_avg = A.nnz / A.n
+        b_gather, _ = algorithmic_bytes(d_avg, {"f32": 4, "bf16": 2, "f64": 8}[args.dtype])
+        res = {}
+        with pc.Problem(A, inst.b, inst.lam, 1, seed=0) as p:
+            r1 = measure_rate(p, 1, min_seconds=0.5)
+            res["1"] = {"us_per_step": r1["us_per_step"], "gather_avg_us": r1["gather_avg_us"],
+                        "scatter_avg_us": r1["scatter_avg_us"], "note": "fixed cost of one step"}
+            for tau in (1024, 65536, 1_000_000):
+                p.set_option("tau", tau)
+                p.set_option("refresh_every", -(-A.n // tau))
+                p.set_x(np.zeros(A.n), k=0)
+                inf = p.info()
+                r = measure_rate(p, tau)
+                r["beta"] = inf["beta"]
+                r["epoch_steps"] = inf["refresh_every"]
+                r["gather_alg_gbps"] = b_gather * tau / (r["gather_avg_us"] * 1e-6) / 1e9
+                p.set_x(np.zeros(A.n), k=0)
+                r["time_to_gap"] = time_to_gap(p, inf["refresh_every"], 1e-6, args.gap_seconds)
+                res[str(tau)] = r
+                print(f"[bench] {cfg} tau={tau}: {r}", file=sys.stderr, flush=True)
+            omega = p.info()["omega"]
+        out["workloads"][WORKLOAD_NAMES[cfg]] = {"m": A.m, "n": A.n, "nnz": A.nnz, "omega": omega, "taus": res}
+        del inst, A
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_samplings(args) -> int:
+    """The samplings on one instance: tau-nice, tau-independent (the paper's
+    own runs), (tau, 0.9)-binomial and tau-nice with 10% of the slots down:
+    distinct coordinate updates/s, kernel times, time to a certified 1e-6 gap."""
+    import numpy as np
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import make_config
+
+    torch.cuda.set_device(0)
+    inst = make_config(args.config, dtype=args.dtype, tau=args.tau)
+    A = inst.A
+    tau = min(args.tau, A.n)
+    rng = np.random.default_rng(0)
+    dead = (rng.random(tau) < 0.1)
+    cases = [("nice", 1.0, None), ("independent", 1.0, None), ("binomial", 0.9, None),
+             ("nice", 1.0, (~dead).astype(np.uint8))]
+    res = {}
+    with pc.Problem(A, inst.b, inst.lam, tau, seed=0) as p:
+        for sampling, pb, mask in cases:
+            name = sampling + ("_mask10" if mask is not None else "") + (f"_p{pb}" if sampling == "binomial" else "")
+            p.set_sampling(sampling, pb)
+            p.set_slot_mask(mask)
+            p.set_x(np.zeros(A.n), k=0)
+            inf = p.info()
+            r = measure_rate(p, tau)
+            es = inf["expected_set_size"] * (1.0 if mask is None else float(mask.mean()))
+            r["expected_set_size"] = es
+            r["distinct_updates_per_s"] = r["slot_updates_per_s"] * es / tau
+            r["beta"] = inf["beta"]
+            p.set_x(np.zeros(A.n), k=0)
+            r["time_to_gap"] = time_to_gap(p, inf["refresh_every"], 1e-6, args.gap_seconds)
+            res[name] = r
+            print(f"[bench] {name}: {r}", file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "mode": "samplings", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": WORKLOAD_NAMES[args.config], "tau": tau}, "samplings": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,9 +336,11 @@ def main() -> int:
     ap.add_argument("--gap-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings"],
                     help="single: one instance (default); batched: the uneven lambda path; "
-                         "dtypes: time to gap with float64 / float32 / bf16 values")
+                         "dtypes: time to gap with float64 / float32 / bf16 values; taus: tau sweep "
+                         "on both 1e7-column instances; samplings: nice / independent / binomial / "
+                         "masked slots")
     ap.add_argument("--count", type=int, default=64, help="problems in the batched mode")
     ap.add_argument("--check-steps", type=int, default=64, help="batched mode: steps between gap checks")
     args = ap.parse_args()
@@ -214,6 +357,10 @@ def main() -> int:
         return run_batched(args)
     if args.mode == "dtypes":
         return run_dtypes(args)
+    if args.mode == "taus":
+        return run_taus(args)
+    if args.mode == "samplings":
+        return run_samplings(args)
 
     import numpy as np
     import torch

@@ -103,6 +103,7 @@ typedef struct pcdm_info {
     double binomial_p;       /* availability p_b of a binomial slot               */
     double expected_set_size;/* E|S_k| of the sampling (drop mask not included)   */
     int64_t mask_len;        /* slots covered by the drop mask (0 = none)         */
+    int64_t narrow_below;    /* tau below which a slot gets a group of lanes      */
 } pcdm_info;
 
 /*
@@ -161,6 +162,12 @@ const char *pcdm_last_error(void);
  *   "chunks_per_lane"  0 = automatic, or 1, 2, 4 four-entry chunks of the
  *                      column each lane keeps in registers; supported pairs
  *                      (lanes, chunks): (1|2, 1|2|4), (4|8, 1|2), (16|32|64, 1);
+ *   "narrow_below"     step-kernel layout: for tau below this value (default
+ *                      131072) each sampled slot gets its own group of
+ *                      lanes_per_column lanes (64/lanes slots per wave), so a
+ *                      small step still spreads over many waves; otherwise a
+ *                      wave owns 64 consecutive slots (one lane each for the
+ *                      sampling and the update).  0 = always 64-slot tiles;
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
  *                      settings of pcdm_grad_backward's solve (see there);
@@ -244,8 +251,9 @@ int pcdm_kernel_time(pcdm_problem *h, const char *kernel, int64_t *launches, dou
 
 /*
  * Schedule autotuner: runs steps_per_candidate real steps (they advance k)
- * with each supported (lanes_per_column, chunks_per_lane) pair, timed with
- * HIP events on `stream`, and keeps the fastest.  Synchronous.
+ * with each supported (lanes_per_column, chunks_per_lane) pair, both with
+ * 64-slot tiles and with a lane group per slot (option "narrow_below"),
+ * timed with HIP events on `stream`, and keeps the fastest.  Synchronous.
  */
 int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream);
 

@@ -139,7 +139,8 @@ class Problem:
         """Time every supported schedule for a few real steps and keep the fastest."""
         check(self._lib.pcdm_autotune(self._h, int(steps_per_candidate), current_stream()))
         inf = self.info()
-        return {"lanes_per_column": inf["lanes_per_column"], "chunks_per_lane": inf["chunks_per_lane"]}
+        return {"lanes_per_column": inf["lanes_per_column"], "chunks_per_lane": inf["chunks_per_lane"],
+                "narrow_below": inf["narrow_below"]}
 
     def kernel_time(self, kernel: str):
         """(launches, total milliseconds) of one kernel kind while timing is on."""

@@ -426,6 +426,155 @@ k_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restr
         scatter_tile<V, G>(seg, lay, r, id_slot, delta_slot, tl, base, tau);
 }
 
+// --------------------------------------------------------------------------
+// Narrow schedule for small tau: one slot per group of G lanes (64/G slots
+// per wave), so tau slots spread over tau*G/64 waves instead of tau/64 and a
+// small step is not left to a handful of waves.  The group leader draws the
+// slot, reads the record header and writes the result; the G lanes read the
+// column's entries as in the tiles.
+// --------------------------------------------------------------------------
+
+template <typename V, int G, int C>
+__device__ __forceinline__ void gather_slot_narrow(char *__restrict__ seg, const Layout &lay,
+                                                   const typename ValT<V>::T *__restrict__ r, double *__restrict__ xm,
+                                                   int32_t *__restrict__ id_slot,
+                                                   typename ValT<V>::T *__restrict__ delta_slot, const NiceKey &key,
+                                                   const SlotDraw &sd, int gl, int leader, int64_t slot,
+                                                   int64_t tau, double inv_beta, double lam, uint64_t &nz)
+{
+    using T = typename ValT<V>::T;
+    const bool act = slot < tau;  // the same for the whole group
+    int live = 0;
+    uint32_t i = 0;
+    int64_t off = 0;
+    int32_t dp = 0;
+    double xi = 0.0, il = 0.0;
+    if (act && gl == 0) {
+        live = draw_slot(sd, key, (uint32_t)slot, i) ? 1 : 0;
+        if (live) {
+            locate<V>(lay, i, off, dp);
+            const double *hdr = reinterpret_cast<const double *>(seg + off);
+            xi = hdr[0];
+            il = hdr[1];
+        }
+    }
+    off = __shfl(off, leader);
+    dp = __shfl(dp, leader);
+    const char *rows = seg + off + kHeader;
+    int rw[C][4];
+    T v[C][4];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int e = 4 * (gl + G * c);
+        if (e < dp) {
+            Chunk4<V>::load(rows, dp, e, rw[c], v[c]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                rw[c][t] = 0;
+                v[c][t] = T(0);
+            }
+        }
+    }
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if (4 * (gl + G * c) < dp) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc += v[c][t] * load_row(r, rw[c][t]);
+        }
+    }
+    for (int e = 4 * (gl + G * C); e < dp; e += 4 * G) {
+        int rr[4];
+        T vv[4];
+        Chunk4<V>::load(rows, dp, e, rr, vv);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc += vv[t] * load_row(r, rr[t]);
+    }
+    const T g = group_sum<G>(acc);
+    if (act && gl == 0) {
+        const double scale = il * inv_beta;
+        const double xn = soft_threshold<double>(xi - (double)g * scale, lam * scale);
+        const double d = live ? xn - xi : 0.0;
+        id_slot[slot] = (int32_t)i;
+        delta_slot[slot] = (T)d;
+        if (d != 0.0) {
+            *reinterpret_cast<double *>(seg + off) = xn;
+            xm[i] = xn;
+            ++nz;
+        }
+    }
+}
+
+template <typename V, int G, int C>
+__global__ void __launch_bounds__(kBlock)
+k_gather_narrow(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
+                double *__restrict__ xm, int32_t *__restrict__ id_slot, typename ValT<V>::T *__restrict__ delta_slot,
+                const Ctrl *__restrict__ ctrl, uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau,
+                uint32_t n, double inv_beta, double lam, SlotPlan plan)
+{
+    __shared__ uint32_t s_keys[kNiceRounds];
+    __shared__ uint64_t s_red[kBlock / 64];
+    constexpr int SPW = 64 / G;
+    const uint64_t k = ctrl->k;
+    const NiceKey key = nice_key_block(seed, k, n, s_keys);
+    const SlotDraw sd = slot_draw_for(plan, seed, k);
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int leader = lane & ~(G - 1);
+    uint64_t nz = 0;
+    for (int64_t base = wave_global_id() * SPW; base < tau; base += wave_count() * SPW)
+        gather_slot_narrow<V, G, C>(seg, lay, r, xm, id_slot, delta_slot, key, sd, gl, leader, base + lane / G, tau,
+                                    inv_beta, lam, nz);
+    const uint64_t tot = block_sum_u64(nz, s_red);
+    if (threadIdx.x == 0 && tot)
+        nz_part[blockIdx.x] += tot;
+}
+
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_scatter_narrow(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restrict__ r,
+                 const int32_t *__restrict__ id_slot, const typename ValT<V>::T *__restrict__ delta_slot,
+                 Ctrl *__restrict__ ctrl, int64_t tau)
+{
+    using T = typename ValT<V>::T;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ctrl->k += 1;  // no block of this kernel reads k
+    constexpr int SPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int leader = lane & ~(G - 1);
+    for (int64_t base = wave_global_id() * SPW; base < tau; base += wave_count() * SPW) {
+        const int64_t slot = base + lane / G;
+        T d = T(0);
+        int32_t id = 0;
+        if (slot < tau && gl == 0) {
+            d = delta_slot[slot];
+            id = id_slot[slot];
+        }
+        d = __shfl(d, leader);
+        id = __shfl(id, leader);
+        if (!__any(d != T(0)))
+            continue;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (d != T(0))
+            locate<V>(lay, id, off, dp);
+        const char *rows = seg + off + kHeader;
+        for (int e = 4 * gl; e < dp; e += 4 * G) {
+            int rw[4];
+            T v[4];
+            Chunk4<V>::load(rows, dp, e, rw, v);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (v[t] != T(0))
+                    atomic_add_hw<T>(r + rw[t], d * v[t]);
+        }
+    }
+}
+
 // The sampler alone (for tests and callers that want S_k).
 __global__ void __launch_bounds__(kBlock)
 k_sample(uint64_t seed, uint64_t step, int64_t tau, uint32_t n, int mode, double pb, int32_t *__restrict__ out)

@@ -95,6 +95,7 @@ struct pcdm_problem {
     int64_t refresh_every = 0;
     int lanes = 8;
     int chunks = 1;
+    int64_t narrow_below = 131072;  // tau below which a slot gets a lane group (not a lane)
     int lanes_auto = 1;
     int nblk_max = 2048;
     hipStream_t last_stream = nullptr;
@@ -355,6 +356,21 @@ template <typename V> struct Ops {
 
     template <int G, int C> static void launch_step(pcdm_problem *P, hipStream_t s)
     {
+        if (P->tau < P->narrow_below) {
+            // one slot per group of G lanes
+            const int grid = grid_for(P->tau * G, kBlock, P->nblk_max);
+            hipEvent_t t0 = clock_start(P, s);
+            hipLaunchKernelGGL((k_gather_narrow<V, G, C>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
+                               (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part, P->seed,
+                               P->tau, (uint32_t)P->n, 1.0 / P->beta, P->lambda, slot_plan(P));
+            clock_stop(P, CLK_GATHER, t0, s);
+            hipEvent_t t1 = clock_start(P, s);
+            hipLaunchKernelGGL((k_scatter_narrow<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg,
+                               P->lay, (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl,
+                               P->tau);
+            clock_stop(P, CLK_SCATTER, t1, s);
+            return;
+        }
         const int grid = grid_for(P->tau, kBlock, P->nblk_max);  // one slot per thread per tile
         hipEvent_t t0 = clock_start(P, s);
         hipLaunchKernelGGL((k_gather<V, G, C>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
@@ -802,6 +818,10 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             return fail(PCDM_EINVAL, "binomial_p must be in (0, 1]");
         h->pb = value;
         compute_beta(h);
+    } else if (k == "narrow_below") {
+        if (!(value >= 0.0))
+            return fail(PCDM_EINVAL, "narrow_below must be >= 0");
+        h->narrow_below = value > 9.0e18 ? INT64_MAX : (int64_t)value;
     } else if (k == "adj_tol") {
         if (!(value > 0.0))
             return fail(PCDM_EINVAL, "adj_tol must be > 0");
@@ -866,6 +886,7 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->binomial_p = h->pb;
     out->expected_set_size = expected_set_size(h);
     out->mask_len = h->mask_len;
+    out->narrow_below = h->narrow_below;
     return PCDM_OK;
 }
 
@@ -1189,31 +1210,42 @@ int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream)
     HIP_TRY(hipEventCreate(&e1));
     float best = std::numeric_limits<float>::max();
     int bg = h->lanes, bc = h->chunks;
+    int64_t bn = h->narrow_below;
     int st = PCDM_OK;
     const int keep_timing = h->timing;
     h->timing = 0;
-    for (const auto &c : cand) {
-        h->lanes = c[0];
-        h->chunks = c[1];
-        (void)hipEventRecord(e0, s);
-        st = pcdm_step(h, steps_per_candidate, stream);
-        (void)hipEventRecord(e1, s);
+    // each schedule with tiles of 64 slots (narrow_below = 0) and with a lane
+    // group per slot (narrow_below above tau)
+    const int64_t widths[2] = {0, INT64_MAX};
+    for (int64_t nb : widths) {
+        for (const auto &c : cand) {
+            h->lanes = c[0];
+            h->chunks = c[1];
+            h->narrow_below = nb;
+            (void)hipEventRecord(e0, s);
+            st = pcdm_step(h, steps_per_candidate, stream);
+            (void)hipEventRecord(e1, s);
+            if (st != PCDM_OK)
+                break;
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                break;
+            if (ms < best) {
+                best = ms;
+                bg = c[0];
+                bc = c[1];
+                bn = nb;
+            }
+        }
         if (st != PCDM_OK)
             break;
-        float ms = 0.f;
-        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-            break;
-        if (ms < best) {
-            best = ms;
-            bg = c[0];
-            bc = c[1];
-        }
     }
     h->timing = keep_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->lanes = bg;
     h->chunks = bc;
+    h->narrow_below = bn;
     h->lanes_auto = 0;
     return st;
 }

@@ -350,3 +350,53 @@ def test_full_size_steps_match_oracle(pc, c2_full):
         assert np.max(np.abs(x - ref.x)) <= 1e-5 * scale
         assert np.array_equal(x != 0, ref.x != 0) or np.mean((x != 0) != (ref.x != 0)) < 1e-5
         _say(f"nonzero updates gpu {p.info()['nonzero_updates']} oracle {ref.changed}")
+
+
+# --------------------------------------------------------------------------- #
+# the two step-kernel layouts (64-slot tiles, a lane group per slot)
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+def test_narrow_and_tiled_layouts_agree(pc, lanes):
+    """The first step from x = 0 reads r = -b only, so both layouts must give
+    the same x bit for bit (same summation order per column); over further
+    steps each stays within 1e-10 of the oracle.  tau = 300 leaves a ragged
+    last tile / wave."""
+    rng = np.random.default_rng(40 + lanes)
+    A = random_csc_ragged(700, 1100, 1, 41, rng)
+    inst = planted_lasso(A, 30, 0.01, 0.05, rng)
+    xs = {}
+    for name, nb in (("tiles", 0), ("narrow", 10**12)):
+        ref = oracle.Solver(inst.A, inst.b, inst.lam, tau=300, seed=8)
+        with pc.Problem(inst.A, inst.b, inst.lam, 300, seed=8) as p:
+            p.set_option("lanes_per_column", lanes)
+            p.set_option("narrow_below", nb)
+            assert p.info()["narrow_below"] == (0 if nb == 0 else nb)
+            p.step(1)
+            xs[name] = p.get_x()
+            ref.step(1)
+            np.testing.assert_allclose(xs[name], ref.x, rtol=0, atol=1e-12)
+            for _ in range(4):
+                p.step(7)
+                ref.step(7)
+                F, _ = p.objective()
+                assert F == pytest.approx(ref.objective(), rel=1e-10)
+            np.testing.assert_allclose(p.get_x(), ref.x, rtol=0, atol=1e-9)
+    assert np.array_equal(xs["tiles"], xs["narrow"])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_narrow_layout_large_tau(pc, dtype):
+    """The lane-group layout forced at tau = 4000 (many waves, grid-stride
+    loop) on float32 / bf16 values, against the oracle."""
+    rng = np.random.default_rng(77)
+    A = random_csc(3000, 5000, 12, rng, dtype=dtype)
+    inst = planted_lasso(A, 50, 0.01, 0.05, rng)
+    ref = oracle.Solver(inst.A, inst.b, inst.lam, tau=4000, seed=1)
+    with pc.Problem(inst.A, inst.b, inst.lam, 4000, seed=1) as p:
+        p.set_option("narrow_below", 10**12)
+        for _ in range(5):
+            p.step(6)
+            ref.step(6)
+            F, _ = p.objective()
+            assert F == pytest.approx(ref.objective(), rel=1e-5)
