@@ -74,6 +74,8 @@ def _lib():
                                           _i64, _I64P]),
                 "orc_independent_moments": (None, [_i64, _i64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
                 "orc_beta_du": (_f64, [_i64, _i64, _f64, _f64]),
+                "orc_async_serial_run": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64, _u64,
+                                                _u64, _i64, _F64P, _F64P]),
                 "orc_pcdm_run_sampling": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64,
                                                  _i64, _u64, _i64, _i64, ctypes.c_int, _f64,
                                                  ctypes.c_void_p, _i64, _F64P, _F64P]),
@@ -321,6 +323,17 @@ class Solver:
 
     def steps_per_epoch(self) -> int:
         return -(-self.n // self.tau)
+
+    def async_serial(self, launch: int, nupdates: int) -> int:
+        """One processor of the asynchronous variant: nupdates serial updates
+        over the pick stream of launch number ``launch`` (independent uniform
+        picks), each applied at once."""
+        c = _lib().orc_async_serial_run(self.m, self.n, self.cp, self.ri, self.v, self.L, self.lam, self.beta,
+                                        self.seed & (2**64 - 1), int(launch), int(nupdates), self.x, self.r)
+        if c < 0:
+            raise RuntimeError("oracle async run failed")
+        self.changed += int(c)
+        return int(c)
 
 
 # --------------------------------------------------------------------------- #

@@ -25,6 +25,8 @@
  *     Samplings" (items "independent sampling", "binomial sampling", implicit
  *     selection); their beta: Table "ESO" (doubly uniform and binomial rows),
  *     theorem "ESO for doubly uniform samplings".
+ *   - the asynchronous variant with one processor: section "Numerical
+ *     experiments" (billion-variable LASSO), serial over independent picks.
  *   - the dual bound for the duality gap is standard LASSO duality.
  *
  * Numerics: float64, round to nearest, sums in ascending index order, no
@@ -525,4 +527,46 @@ int64_t orc_pcdm_run_sampling(int64_t m, int64_t n, const int64_t *col_ptr, cons
     }
     free(S);
     return total;
+}
+
+/*
+ * Asynchronous variant with one processor (section "Numerical experiments",
+ * LASSO with a billion variables: the implementation there lets each core
+ * read the current iterate when it is ready and apply its update at once,
+ * each core picking a block uniformly and independently).  With a single
+ * processor every update sees all earlier ones, so the run is serial
+ * coordinate descent over the pick stream
+ *     i_u = floor(u64 * n / 2^64),  u64 = SplitMix64 output u of the stream
+ *     started at kappa, kappa = SplitMix64 output `launch` of the stream
+ *     started at seed XOR 0x5043444D4153594E,
+ * for updates u = 0 .. nupdates-1 of launch number `launch`.  Each update is
+ * the damped soft-threshold step of PCDM1 with the given beta.  x and
+ * r = A x - b are updated in place.  Returns the number of changed
+ * coordinates' updates, or -1.
+ */
+int64_t orc_async_serial_run(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                             const double *val, const double *L, double lambda, double beta, uint64_t seed,
+                             uint64_t launch, int64_t nupdates, double *x, double *r)
+{
+    uint64_t kappa = orc_splitmix64(seed ^ 0x5043444D4153594EULL, launch);
+    int64_t changed = 0;
+    (void)m;
+    if (n < 1 || n > 2147483647LL || nupdates < 0)
+        return -1;
+    for (int64_t u = 0; u < nupdates; ++u) {
+        uint64_t w = orc_splitmix64(kappa, (uint64_t)u);
+        int64_t i = (int64_t)(((unsigned __int128)w * (uint64_t)n) >> 64);
+        double g = 0.0, xn, d;
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            g += val[p] * r[row_idx[p]];
+        xn = orc_soft(x[i] - g / (beta * L[i]), lambda / (beta * L[i]));
+        d = xn - x[i];
+        if (d == 0.0)
+            continue;
+        ++changed;
+        x[i] = xn;
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            r[row_idx[p]] += d * val[p];
+    }
+    return changed;
 }
