@@ -321,6 +321,70 @@ def run_samplings(args) -> int:
     return 0
 
 
+def async_time_to_gap(p, target: float, limit_s: float, check_every: int = 5) -> dict:
+    """Wall time of asynchronous epochs (n picks each, float64 refresh after
+    each) until the certified gap (F - D)/D <= target, checked every
+    `check_every` epochs (inside the timed region)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    epochs = 0
+    rel = float("inf")
+    F = None
+    while time.perf_counter() - t0 < limit_s:
+        p.step_async(check_every)
+        epochs += check_every
+        F, gap = p.objective(gap=True)
+        rel = gap / max(abs(F - gap), 1e-300)
+        if rel <= target:
+            break
+    return {"target_rel_gap": target, "reached": bool(rel <= target), "seconds": time.perf_counter() - t0,
+            "epochs": epochs, "rel_gap": rel, "F": F, "check_every_epochs": check_every}
+
+
+def run_async(args) -> int:
+    """Asynchronous variant vs synchronous steps on one instance, per tau:
+    picks/s, and time to a certified 1e-6 gap from x = 0."""
+    import numpy as np
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import make_config
+
+    torch.cuda.set_device(0)
+    inst = make_config(args.config, dtype=args.dtype)
+    A = inst.A
+    res = {}
+    with pc.Problem(A, inst.b, inst.lam, 1024, seed=0) as p:
+        for tau in (1024, 65536, 1_000_000):
+            tau = min(tau, A.n)
+            p.set_option("tau", tau)
+            p.set_option("refresh_every", -(-A.n // tau))
+            p.set_x(np.zeros(A.n), k=0)
+            sync = time_to_gap(p, -(-A.n // tau), 1e-6, args.gap_seconds)
+            r_tau = {"beta": p.info()["beta"], "sync_time_to_gap": sync}
+            for label, reads, rounds in (("default", -1, 4), ("cached_r1", 0, 1), ("cached_r4", 0, 4),
+                                         ("acquire", 1, 0), ("atomic", 2, 0)):
+                p.set_option("async_reads", reads)
+                p.set_option("async_rounds", rounds)
+                p.set_x(np.zeros(A.n), k=0)
+                p.step_async(1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                p.step_async(2)
+                torch.cuda.synchronize()
+                rate = 2 * A.n / (time.perf_counter() - t0)
+                p.set_x(np.zeros(A.n), k=0)
+                r_tau[label] = {"picks_per_s": rate, "processors": p.info()["async_processors"],
+                                "time_to_gap": async_time_to_gap(p, 1e-6, args.gap_seconds)}
+                print(f"[bench] async tau={tau} {label}: {r_tau[label]}", file=sys.stderr, flush=True)
+            res[str(tau)] = r_tau
+    out = {"metric": METRIC, "mode": "async", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": WORKLOAD_NAMES[args.config]}, "taus": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,11 +400,11 @@ def main() -> int:
     ap.add_argument("--gap-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async"],
                     help="single: one instance (default); batched: the uneven lambda path; "
                          "dtypes: time to gap with float64 / float32 / bf16 values; taus: tau sweep "
                          "on both 1e7-column instances; samplings: nice / independent / binomial / "
-                         "masked slots")
+                         "masked slots; async: asynchronous variant vs synchronous steps")
     ap.add_argument("--count", type=int, default=64, help="problems in the batched mode")
     ap.add_argument("--check-steps", type=int, default=64, help="batched mode: steps between gap checks")
     args = ap.parse_args()
@@ -361,6 +425,8 @@ def main() -> int:
         return run_taus(args)
     if args.mode == "samplings":
         return run_samplings(args)
+    if args.mode == "async":
+        return run_async(args)
 
     import numpy as np
     import torch

@@ -104,6 +104,8 @@ typedef struct pcdm_info {
     double expected_set_size;/* E|S_k| of the sampling (drop mask not included)   */
     int64_t mask_len;        /* slots covered by the drop mask (0 = none)         */
     int64_t narrow_below;    /* tau below which a slot gets a group of lanes      */
+    int64_t async_picks;     /* picks made by pcdm_step_async so far              */
+    int64_t async_processors;/* processors (lane groups) of its last launch       */
 } pcdm_info;
 
 /*
@@ -168,6 +170,9 @@ const char *pcdm_last_error(void);
  *                      small step still spreads over many waves; otherwise a
  *                      wave owns 64 consecutive slots (one lane each for the
  *                      sampling and the update).  0 = always 64-slot tiles;
+ *   "async_processors" processors of pcdm_step_async: 0 (default) = min(tau,
+ *                      lane groups the device holds at once), else that count;
+ *   "async_reads", "async_rounds": see pcdm_step_async;
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
  *                      settings of pcdm_grad_backward's solve (see there);
@@ -187,6 +192,35 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out);
  * float64 from x and rounded to the working type.  Asynchronous.
  */
 int pcdm_step(pcdm_problem *h, int64_t nsteps, void *stream);
+
+/*
+ * Asynchronous variant (section "Numerical experiments", billion-variable
+ * LASSO: the timed implementation lets each core read the current iterate
+ * when it is ready and apply its update at once, each core picking a block
+ * uniformly and independently).  One call makes `picks` picks spread over P
+ * processors (groups of lanes_per_column lanes; option "async_processors"):
+ * pick u of call c is block floor(w n / 2^64), w = SplitMix64 output u from
+ * kappa_c = SplitMix64 output c from seed ^ 0x5043444D4153594E (c counts this
+ * handle's calls from 0), and processor p makes picks p, p + P, ...  Each
+ * pick takes its block by an atomic swap on x_i's slot (a block held by
+ * another processor is skipped for that pick), reads r, releases the block
+ * by swapping in the new x_i and adds delta_i a_i to r with float atomics.
+ * No step boundary: reads see the updates that have landed.  Because each
+ * XCD has its own L2, option "async_reads" sets how fresh reads of r are:
+ * 0 = plain cached loads, with the call split into launches of
+ * "async_rounds" rounds of P picks (default 4; 0 = one launch), whose
+ * boundaries make all earlier updates visible; 1 = the swap that takes a
+ * block is an acquire (caches invalidated before the reads); 2 = r read
+ * through returning atomics; -1 (default) = 1 for at most 8192 processors,
+ * else 0.  x lives only in the column records during a launch; the dense
+ * copy behind pcdm_get_x is rebuilt from them at the end of the call.  beta is the handle's (the tau-nice rule with
+ * tau = the handle's tau, as the paper's runs used with tau = cores).  With
+ * P = 1 the call is serial coordinate descent over the pick stream.
+ * Afterwards, if refresh_every > 0, r is recomputed in float64.  Does not
+ * advance k.  Asynchronous; the result depends on timing for P > 1.  No
+ * other work may touch the handle while a call runs.
+ */
+int pcdm_step_async(pcdm_problem *h, int64_t picks, void *stream);
 
 /*
  * F(x) = 0.5||A x - b||^2 + lambda||x||_1 with A x - b recomputed in float64
@@ -242,7 +276,8 @@ int pcdm_set_rhs(pcdm_problem *h, const double *b, int32_t on_device, void *stre
 /*
  * Device time of one kernel kind of the step while option "kernel_timing" is
  * on: kernel = "gather" (sample, partial derivatives, update of x),
- * "scatter" (residual scatter-add) or "refresh" (float64 residual refresh).
+ * "scatter" (residual scatter-add), "refresh" (float64 residual refresh) or
+ * "async" (launches of pcdm_step_async).
  * Measured between HIP events recorded on the launch stream just before and
  * after each launch.  Waits for the recorded launches; writes the number of
  * launches and their summed milliseconds since timing was (re)started.

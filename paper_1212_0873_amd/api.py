@@ -112,6 +112,13 @@ class Problem:
     def set_option(self, key: str, value: float) -> None:
         check(self._lib.pcdm_set_option(self._h, key.encode(), float(value)))
 
+    def step_async(self, epochs: int = 1, picks_per_epoch: Optional[int] = None) -> None:
+        """Epochs of the asynchronous variant: each one launch of n picks
+        (or ``picks_per_epoch``) followed by the float64 refresh."""
+        picks = self.n if picks_per_epoch is None else int(picks_per_epoch)
+        for _ in range(int(epochs)):
+            check(self._lib.pcdm_step_async(self._h, picks, current_stream()))
+
     def set_sampling(self, sampling: str, pb: float = 1.0) -> None:
         """'nice', 'independent' or 'binomial' (availability pb); beta follows
         the sampling unless an explicit beta was set."""

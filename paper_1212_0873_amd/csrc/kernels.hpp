@@ -434,6 +434,63 @@ k_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restr
 // column's entries as in the tiles.
 // --------------------------------------------------------------------------
 
+// This lane's share of a_i^T r for a column of dp (padded) entries whose rows
+// start at `rows`, read by the G lanes of a group (lane gl takes chunks gl,
+// gl + G, ...; C of them loaded before any dependent gather).
+// Reads of r in the asynchronous kernel: kReadCached = ordinary loads (they
+// may return a line the XCD's L2 holds from before other XCDs' atomics);
+// kReadAtomic = a returning atomic add of zero, performed where the
+// scatter-adds are, so it sees every add that has landed.
+enum : int { kReadCached = 0, kReadAcquire = 1, kReadAtomic = 2 };
+
+template <typename T, int Mode> __device__ __forceinline__ T load_r(const T *base, int row)
+{
+    if constexpr (Mode == kReadAtomic)
+        return unsafeAtomicAdd(const_cast<T *>(base) + (uint32_t)row, T(0));
+    else
+        return load_row(base, row);
+}
+
+template <typename V, int G, int C, int Fresh = kReadCached>
+__device__ __forceinline__ typename ValT<V>::T lane_dot(const char *rows, int32_t dp, int gl,
+                                                        const typename ValT<V>::T *r)
+{
+    using T = typename ValT<V>::T;
+    int rw[C][4];
+    T v[C][4];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int e = 4 * (gl + G * c);
+        if (e < dp) {
+            Chunk4<V>::load(rows, dp, e, rw[c], v[c]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                rw[c][t] = 0;
+                v[c][t] = T(0);
+            }
+        }
+    }
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if (4 * (gl + G * c) < dp) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc += v[c][t] * load_r<T, Fresh>(r, rw[c][t]);
+        }
+    }
+    for (int e = 4 * (gl + G * C); e < dp; e += 4 * G) {
+        int rr[4];
+        T vv[4];
+        Chunk4<V>::load(rows, dp, e, rr, vv);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc += vv[t] * load_r<T, Fresh>(r, rr[t]);
+    }
+    return acc;
+}
+
 template <typename V, int G, int C>
 __device__ __forceinline__ void gather_slot_narrow(char *__restrict__ seg, const Layout &lay,
                                                    const typename ValT<V>::T *__restrict__ r, double *__restrict__ xm,
@@ -460,40 +517,7 @@ __device__ __forceinline__ void gather_slot_narrow(char *__restrict__ seg, const
     }
     off = __shfl(off, leader);
     dp = __shfl(dp, leader);
-    const char *rows = seg + off + kHeader;
-    int rw[C][4];
-    T v[C][4];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int e = 4 * (gl + G * c);
-        if (e < dp) {
-            Chunk4<V>::load(rows, dp, e, rw[c], v[c]);
-        } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                rw[c][t] = 0;
-                v[c][t] = T(0);
-            }
-        }
-    }
-    T acc = T(0);
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        if (4 * (gl + G * c) < dp) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc += v[c][t] * load_row(r, rw[c][t]);
-        }
-    }
-    for (int e = 4 * (gl + G * C); e < dp; e += 4 * G) {
-        int rr[4];
-        T vv[4];
-        Chunk4<V>::load(rows, dp, e, rr, vv);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            acc += vv[t] * load_row(r, rr[t]);
-    }
-    const T g = group_sum<G>(acc);
+    const T g = group_sum<G>(lane_dot<V, G, C>(seg + off + kHeader, dp, gl, r));
     if (act && gl == 0) {
         const double scale = il * inv_beta;
         const double xn = soft_threshold<double>(xi - (double)g * scale, lam * scale);
@@ -575,6 +599,107 @@ k_scatter_narrow(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *
     }
 }
 
+// --------------------------------------------------------------------------
+// Asynchronous variant (the implementation behind the paper's
+// billion-variable LASSO timings): no phase boundary inside a launch.  Each
+// group of G lanes is a processor that repeatedly picks a block uniformly and
+// independently, reads x_i and r, and applies its update to x_i and r at
+// once.  The x_i slot of the column record is also the block's lock: a
+// processor takes block i by atomically swapping a reserved NaN pattern into
+// it (the old value is the current x_i) and releases it by swapping in the
+// new value, so acquisition, the read of x_i and its write are atomic
+// operations on one address.  A processor whose pick is held by another idles
+// for that pick (as when two cores pick the same block).  Only the records
+// hold x during the launch: plain stores from several XCDs to one mirror
+// entry could land in either order, so the host rebuilds the mirror from the
+// records afterwards.
+// Each XCD has its own L2, so a plain load of r can return a line cached
+// before other XCDs' scatter-adds; how fresh the reads are is the Mode:
+// kReadCached (plain loads; the host bounds staleness by ending the launch
+// every few rounds), kReadAcquire (the swap that takes a block has acquire
+// semantics, which invalidates the caches before the reads), kReadAtomic
+// (r read through returning atomics).  Every processor makes a fixed number
+// of picks and no lane waits on another, so every wave ends.
+//   pick u of call c: i = floor(w n / 2^64), w = SplitMix64 output u of the
+//   stream started at kappa_c = SplitMix64 output c of the stream started at
+//   seed ^ 0x5043444D4153594E; this launch makes picks u0 .. u0+picks-1, and
+//   processor p picks u0 + p, u0 + p + P, ...
+// --------------------------------------------------------------------------
+constexpr uint64_t kAsyncStream = 0x5043444D4153594Eull;
+constexpr uint64_t kHeldBits = 0x7FF4C0DE7FF4C0DEull;  // a NaN: x values are finite
+
+template <typename V, int G, int C, int Mode>
+__global__ void __launch_bounds__(kBlock)
+k_async(char *__restrict__ seg, Layout lay, typename ValT<V>::T *r, uint64_t *__restrict__ nz_part, uint64_t seed, uint64_t call, int64_t u0, int64_t picks, int64_t procs,
+        uint32_t n, double inv_beta, double lam)
+{
+    using T = typename ValT<V>::T;
+    __shared__ uint64_t s_red[kBlock / 64];
+    constexpr int GPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int leader = lane & ~(G - 1);
+    const int64_t p = wave_global_id() * GPW + lane / G;
+    const uint64_t kappa = splitmix_output(seed ^ kAsyncStream, call);
+    const int64_t rounds = (picks + procs - 1) / procs;
+    uint64_t nz = 0;
+    for (int64_t t = 0; t < rounds; ++t) {
+        const int64_t u = t * procs + p;
+        int got = 0;
+        uint32_t i = 0;
+        int64_t off = 0;
+        int32_t dp = 0;
+        double xi = 0.0, il = 0.0;
+        if (gl == 0 && p < procs && u < picks) {
+            i = (uint32_t)__umul64hi(splitmix_output(kappa, (uint64_t)(u0 + u)), (uint64_t)n);
+            locate<V>(lay, i, off, dp);
+            uint64_t *slot = reinterpret_cast<uint64_t *>(seg + off);
+            uint64_t old;
+            if constexpr (Mode == kReadAcquire)
+                old = __hip_atomic_exchange(slot, kHeldBits, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                old = __hip_atomic_exchange(slot, kHeldBits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            got = old != kHeldBits;
+            if (got) {
+                xi = __longlong_as_double((long long)old);
+                il = reinterpret_cast<const double *>(seg + off)[1];
+            } else {
+                dp = 0;
+            }
+        }
+        off = __shfl(off, leader);
+        dp = __shfl(dp, leader);
+        const T g = group_sum<G>(lane_dot<V, G, C, Mode>(seg + off + kHeader, dp, gl, r));
+        double d = 0.0;
+        if (got) {
+            const double scale = il * inv_beta;
+            const double xn = soft_threshold<double>(xi - (double)g * scale, lam * scale);
+            d = xn - xi;
+            uint64_t *slot = reinterpret_cast<uint64_t *>(seg + off);
+            (void)__hip_atomic_exchange(slot, (uint64_t)__double_as_longlong(xn), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (d != 0.0)
+                ++nz;
+        }
+        const T dq = (T)__shfl(d, leader);
+        if (dq != T(0)) {
+            const char *rows = seg + off + kHeader;
+            for (int e = 4 * gl; e < dp; e += 4 * G) {
+                int rw[4];
+                T v[4];
+                Chunk4<V>::load(rows, dp, e, rw, v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (v[q] != T(0))
+                        atomic_add_hw<T>(r + rw[q], dq * v[q]);
+            }
+        }
+    }
+    const uint64_t tot = block_sum_u64(nz, s_red);
+    if (threadIdx.x == 0 && tot)
+        nz_part[blockIdx.x] += tot;
+}
+
 // The sampler alone (for tests and callers that want S_k).
 __global__ void __launch_bounds__(kBlock)
 k_sample(uint64_t seed, uint64_t step, int64_t tau, uint32_t n, int mode, double pb, int32_t *__restrict__ out)
@@ -638,6 +763,20 @@ k_x_to_records(char *__restrict__ seg, Layout lay, const double *__restrict__ xm
         int32_t dp;
         locate<V>(lay, i, off, dp);
         *reinterpret_cast<double *>(seg + off) = xm[i];
+    }
+}
+
+// The dense x mirror from the records (after the asynchronous kernel, which
+// writes x only in the records).
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_records_to_x(const char *__restrict__ seg, Layout lay, double *__restrict__ xm, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        int64_t off;
+        int32_t dp;
+        locate<V>(lay, i, off, dp);
+        xm[i] = *reinterpret_cast<const double *>(seg + off);
     }
 }
 

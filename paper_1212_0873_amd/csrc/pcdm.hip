@@ -70,6 +70,7 @@ int grid_for(int64_t items, int64_t per_block, int cap)
 }
 
 constexpr int kReduceBlocks = 1024;
+constexpr int64_t kAsyncAcquireProcs = 8192;  // automatic read mode: acquire up to this many processors
 
 // Device time of one kernel kind, from HIP events recorded around each launch.
 struct KernelClock {
@@ -78,7 +79,7 @@ struct KernelClock {
     double total_ms = 0.0;
 };
 
-enum { CLK_GATHER = 0, CLK_SCATTER = 1, CLK_REFRESH = 2, CLK_COUNT = 3 };
+enum { CLK_GATHER = 0, CLK_SCATTER = 1, CLK_REFRESH = 2, CLK_ASYNC = 3, CLK_COUNT = 4 };
 
 }  // namespace
 
@@ -124,6 +125,15 @@ struct pcdm_problem {
     int64_t mask_len = 0;
     uint32_t *claim = nullptr; // [n] claim stamps for independent picks
     int64_t claim_base = 0;    // step at which claim was last zeroed
+
+    // asynchronous variant
+    int cus = 0;
+    int async_reads = -1;      // kReadCached / kReadAcquire / kReadAtomic, -1 = by processor count
+    int64_t async_rounds = 4;  // rounds of picks per launch with cached reads (0 = the whole call)
+    int64_t async_launches = 0;
+    int64_t async_picks = 0;
+    int64_t async_procs_opt = 0;   // 0 = min(tau, resident lane groups)
+    int64_t async_procs_last = 0;
 
     // adjoint solve settings
     double adj_tol = 1e-6;
@@ -384,6 +394,74 @@ template <typename V> struct Ops {
         clock_stop(P, CLK_SCATTER, t1, s);
     }
 
+    // One call of the asynchronous variant: `picks` picks over P processors
+    // (lane groups), in launches of async_rounds rounds; returns P.
+    template <int G, int C> static int64_t launch_async(pcdm_problem *P, int64_t picks, hipStream_t s)
+    {
+        int mode = P->async_reads;
+        if (mode < 0) {
+            // few processors: each pick's latency chain dominates, fresh reads
+            // through the acquire cost little; many: plain reads, launch
+            // boundaries every few rounds
+            const int64_t want = P->async_procs_opt > 0 ? P->async_procs_opt : P->tau;
+            mode = want <= kAsyncAcquireProcs ? kReadAcquire : kReadCached;
+        }
+        switch (mode) {
+        case kReadAcquire: return launch_async_as<G, C, kReadAcquire>(P, picks, s);
+        case kReadAtomic: return launch_async_as<G, C, kReadAtomic>(P, picks, s);
+        default: return launch_async_as<G, C, kReadCached>(P, picks, s);
+        }
+    }
+
+    template <int G, int C, int Mode> static int64_t launch_async_as(pcdm_problem *P, int64_t picks, hipStream_t s)
+    {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_async<V, G, C, Mode>, kBlock, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        const int64_t gpb = (kBlock / 64) * (64 / G);  // lane groups per block
+        const int64_t resident = (int64_t)per_cu * std::max(P->cus, 1) * gpb;
+        int64_t procs = P->async_procs_opt > 0 ? P->async_procs_opt : std::min<int64_t>(P->tau, resident);
+        procs = std::max<int64_t>(1, std::min<int64_t>(procs, picks));
+        const int64_t blocks = std::min<int64_t>(ceil_div(procs, gpb), P->nblk_max);
+        procs = std::min<int64_t>(procs, blocks * gpb);
+        const int64_t per_launch = (Mode == kReadCached && P->async_rounds > 0) ? P->async_rounds * procs : picks;
+        for (int64_t u0 = 0; u0 < picks; u0 += per_launch) {
+            const int64_t cnt = std::min(per_launch, picks - u0);
+            hipEvent_t t0 = clock_start(P, s);
+            hipLaunchKernelGGL((k_async<V, G, C, Mode>), dim3((unsigned)blocks), dim3(kBlock), 0, s, P->seg, P->lay,
+                               (T *)P->r, P->nz_part, P->seed, (uint64_t)P->async_launches, u0, cnt, procs,
+                               (uint32_t)P->n, 1.0 / P->beta, P->lambda);
+            clock_stop(P, CLK_ASYNC, t0, s);
+        }
+        const int gn = grid_for(P->n, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_records_to_x<V>), dim3(gn), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, P->x,
+                           P->n);
+        return procs;
+    }
+
+    static int async_once(pcdm_problem *P, int64_t picks, hipStream_t s, int64_t &procs)
+    {
+        switch (P->lanes * 16 + P->chunks) {
+        case 1 * 16 + 1: procs = launch_async<1, 1>(P, picks, s); break;
+        case 1 * 16 + 2: procs = launch_async<1, 2>(P, picks, s); break;
+        case 1 * 16 + 4: procs = launch_async<1, 4>(P, picks, s); break;
+        case 2 * 16 + 1: procs = launch_async<2, 1>(P, picks, s); break;
+        case 2 * 16 + 2: procs = launch_async<2, 2>(P, picks, s); break;
+        case 2 * 16 + 4: procs = launch_async<2, 4>(P, picks, s); break;
+        case 4 * 16 + 1: procs = launch_async<4, 1>(P, picks, s); break;
+        case 4 * 16 + 2: procs = launch_async<4, 2>(P, picks, s); break;
+        case 8 * 16 + 1: procs = launch_async<8, 1>(P, picks, s); break;
+        case 8 * 16 + 2: procs = launch_async<8, 2>(P, picks, s); break;
+        case 16 * 16 + 1: procs = launch_async<16, 1>(P, picks, s); break;
+        case 32 * 16 + 1: procs = launch_async<32, 1>(P, picks, s); break;
+        case 64 * 16 + 1: procs = launch_async<64, 1>(P, picks, s); break;
+        default: return fail(PCDM_EINVAL, "unsupported (lanes_per_column, chunks_per_lane) pair");
+        }
+        return PCDM_OK;
+    }
+
     static int step_once(pcdm_problem *P, hipStream_t s)
     {
         switch (P->lanes * 16 + P->chunks) {
@@ -596,6 +674,7 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device));
     P->nblk_max = std::max(64, cus * 8);
+    P->cus = cus;
     P->m = A->m;
     P->n = A->n;
     P->nnz = A->nnz;
@@ -818,6 +897,18 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             return fail(PCDM_EINVAL, "binomial_p must be in (0, 1]");
         h->pb = value;
         compute_beta(h);
+    } else if (k == "async_processors") {
+        if (!(value >= 0.0) || value > 9.0e15)
+            return fail(PCDM_EINVAL, "async_processors must be >= 0");
+        h->async_procs_opt = (int64_t)value;
+    } else if (k == "async_reads") {
+        if (value != -1.0 && value != 0.0 && value != 1.0 && value != 2.0)
+            return fail(PCDM_EINVAL, "async_reads must be -1 (automatic), 0 (cached), 1 (acquire) or 2 (atomic)");
+        h->async_reads = (int)value;
+    } else if (k == "async_rounds") {
+        if (!(value >= 0.0) || value > 9.0e15 || value != std::floor(value))
+            return fail(PCDM_EINVAL, "async_rounds must be a non-negative integer");
+        h->async_rounds = (int64_t)value;
     } else if (k == "narrow_below") {
         if (!(value >= 0.0))
             return fail(PCDM_EINVAL, "narrow_below must be >= 0");
@@ -887,6 +978,8 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->expected_set_size = expected_set_size(h);
     out->mask_len = h->mask_len;
     out->narrow_below = h->narrow_below;
+    out->async_picks = h->async_picks;
+    out->async_processors = h->async_procs_last;
     return PCDM_OK;
 }
 
@@ -907,6 +1000,27 @@ int pcdm_step(pcdm_problem *h, int64_t nsteps, void *stream)
             PCDM_TRY(refresh_now(h, s));
     }
     return check_launch("pcdm_step");
+}
+
+int pcdm_step_async(pcdm_problem *h, int64_t picks, void *stream)
+{
+    if (!h)
+        return fail(PCDM_EINVAL, "NULL handle");
+    if (picks < 0)
+        return fail(PCDM_EINVAL, "picks must be >= 0");
+    if (picks == 0)
+        return PCDM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    int64_t procs = 0;
+    PCDM_TRY(dispatch(h->dtype, [&](auto ops) { return decltype(ops)::async_once(h, picks, s, procs); }));
+    PCDM_TRY(check_launch("pcdm_step_async"));
+    h->async_launches += 1;
+    h->async_picks += picks;
+    h->async_procs_last = procs;
+    if (h->refresh_every > 0)
+        PCDM_TRY(refresh_now(h, s));
+    return PCDM_OK;
 }
 
 int pcdm_objective(pcdm_problem *h, double *F, double *dual_gap, void *stream)
@@ -1189,9 +1303,13 @@ int pcdm_kernel_time(pcdm_problem *h, const char *kernel, int64_t *launches, dou
     if (!h || !kernel || !launches || !total_ms)
         return fail(PCDM_EINVAL, "NULL argument");
     const std::string k(kernel);
-    int kind = k == "gather" ? CLK_GATHER : k == "scatter" ? CLK_SCATTER : k == "refresh" ? CLK_REFRESH : -1;
+    int kind = k == "gather" ? CLK_GATHER
+               : k == "scatter" ? CLK_SCATTER
+               : k == "refresh" ? CLK_REFRESH
+               : k == "async"   ? CLK_ASYNC
+                                : -1;
     if (kind < 0)
-        return fail(PCDM_EINVAL, "kernel must be \"gather\", \"scatter\" or \"refresh\"");
+        return fail(PCDM_EINVAL, "kernel must be \"gather\", \"scatter\", \"refresh\" or \"async\"");
     PCDM_TRY(clock_collect(h, kind));
     *launches = h->clocks[kind].launches;
     *total_ms = h->clocks[kind].total_ms;
