@@ -76,6 +76,18 @@ def _lib():
                 "orc_beta_du": (_f64, [_i64, _i64, _f64, _f64]),
                 "orc_async_serial_run": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64, _u64,
                                                 _u64, _i64, _F64P, _F64P]),
+                "orc_loss_value": (_f64, [ctypes.c_int, _f64, _f64]),
+                "orc_loss_deriv": (_f64, [ctypes.c_int, _f64, _f64]),
+                "orc_loss_curvature_bound": (_f64, [ctypes.c_int]),
+                "orc_model_prox": (_f64, [_f64, _f64, _f64, _f64, _f64, _f64, _f64]),
+                "orc_model_omega": (_f64, [_i64, _F64P, _f64, _f64, _f64, _f64, _f64]),
+                "orc_model_objective": (_f64, [_i64, _i64, _F64P, _F64P, _F64P, ctypes.c_int, _f64, _f64, _f64,
+                                               _f64, _f64, _f64]),
+                "orc_model_step_with_set": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _F64P, ctypes.c_int,
+                                                   _f64, _f64, _f64, _f64, _f64, _f64, _f64, _i64, _I64P, _F64P,
+                                                   _F64P]),
+                "orc_model_run": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _F64P, ctypes.c_int, _f64, _f64,
+                                         _f64, _f64, _f64, _f64, _f64, _i64, _u64, _i64, _i64, _F64P, _F64P]),
                 "orc_pcdm_run_sampling": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64,
                                                  _i64, _u64, _i64, _i64, ctypes.c_int, _f64,
                                                  ctypes.c_void_p, _i64, _F64P, _F64P]),
@@ -363,3 +375,87 @@ def lasso_adjoint(A, x, g):
         v = np.linalg.lstsq(G, g[S], rcond=None)[0]
     s = np.sign(x[S])
     return np.asarray(M @ v).ravel(), float(-(s @ v))
+
+
+# --------------------------------------------------------------------------- #
+# other losses and regularisers
+# --------------------------------------------------------------------------- #
+
+LOSSES = {"square": 0, "logistic": 1, "sqhinge": 2}
+
+
+def loss_value(loss: str, z: float, y: float) -> float:
+    return _lib().orc_loss_value(LOSSES[loss], float(z), float(y))
+
+
+def loss_deriv(loss: str, z: float, y: float) -> float:
+    return _lib().orc_loss_deriv(LOSSES[loss], float(z), float(y))
+
+
+def loss_curvature_bound(loss: str) -> float:
+    return _lib().orc_loss_curvature_bound(LOSSES[loss])
+
+
+def model_prox(v, bl, l1=0.0, l2=0.0, c=0.0, lo=-np.inf, hi=np.inf) -> float:
+    """argmin_u (bl/2)(u - v)^2 + l1|u| + (l2/2)u^2 + c u over lo <= u <= hi."""
+    return _lib().orc_model_prox(float(v), float(bl), float(l1), float(l2), float(c), float(lo), float(hi))
+
+
+class ModelSolver:
+    """Serial float64 PCDM1 on F(x) = s sum_j phi(z_j, y_j) + sum_i Omega_i(x_i),
+    z = A x, with the tau-nice sampler and beta of the tau-nice row.
+
+    ``loss``: 'square' (y = targets), 'logistic' or 'sqhinge' (y = labels
+    +-1); Omega_i(t) = l1|t| + (l2/2)t^2 + c t + indicator(lo <= t <= hi)."""
+
+    def __init__(self, A, y, tau, seed=0, loss="square", scale=1.0, l1=0.0, l2=0.0, c=0.0,
+                 lo=-np.inf, hi=np.inf, beta=None):
+        self.A = A
+        self.m, self.n = A.m, A.n
+        self.cp, self.ri, self.v = _arrays(A)
+        self.y = np.ascontiguousarray(y, np.float64)
+        self.loss = loss
+        self.s, self.l1, self.l2, self.c, self.lo, self.hi = (float(scale), float(l1), float(l2), float(c),
+                                                              float(lo), float(hi))
+        self.tau = int(tau)
+        self.seed = int(seed)
+        self.L = np.empty(self.n)
+        _lib().orc_lipschitz(self.n, self.cp, self.v, self.L)
+        self.L *= self.s * loss_curvature_bound(loss)
+        self.omega = int(_lib().orc_omega(self.m, self.n, self.cp, self.ri, self.v))
+        self.beta = beta_nice(self.omega, self.tau, self.n) if beta is None else float(beta)
+        self.x = np.zeros(self.n)
+        self.z = np.zeros(self.m)
+        self.k = 0
+        self.changed = 0
+
+    def _margins(self):
+        z = np.empty(self.m)
+        _lib().orc_residual(self.m, self.n, self.cp, self.ri, self.v, self.x, np.zeros(self.m), z)
+        return z
+
+    def step(self, nsteps: int = 1) -> int:
+        c = _lib().orc_model_run(self.m, self.n, self.cp, self.ri, self.v, self.L, self.y, LOSSES[self.loss],
+                                 self.s, self.l1, self.l2, self.c, self.lo, self.hi, self.beta, self.tau,
+                                 self.seed & (2**64 - 1), self.k, int(nsteps), self.x, self.z)
+        if c < 0:
+            raise RuntimeError("oracle model step failed")
+        self.k += int(nsteps)
+        self.changed += int(c)
+        return int(c)
+
+    def step_with_set(self, S) -> int:
+        S = np.ascontiguousarray(S, dtype=np.int64)
+        c = _lib().orc_model_step_with_set(self.m, self.n, self.cp, self.ri, self.v, self.L, self.y,
+                                           LOSSES[self.loss], self.s, self.l1, self.l2, self.c, self.lo,
+                                           self.hi, self.beta, S.size, S, self.x, self.z)
+        if c < 0:
+            raise ValueError("bad set")
+        return int(c)
+
+    def objective(self) -> float:
+        return _lib().orc_model_objective(self.m, self.n, self._margins(), self.y, self.x, LOSSES[self.loss],
+                                          self.s, self.l1, self.l2, self.c, self.lo, self.hi)
+
+    def steps_per_epoch(self) -> int:
+        return -(-self.n // self.tau)

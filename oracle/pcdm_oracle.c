@@ -27,6 +27,10 @@
  *     theorem "ESO for doubly uniform samplings".
  *   - the asynchronous variant with one processor: section "Numerical
  *     experiments" (billion-variable LASSO), serial over independent picks.
+ *   - other losses and regularisers: the table of three losses
+ *     (introduction), the SVM dual with box constraints and L2-regularised
+ *     logistic regression (numerical experiments); block minimisers derived
+ *     in orc_model_prox.
  *   - the dual bound for the duality gap is standard LASSO duality.
  *
  * Numerics: float64, round to nearest, sums in ascending index order, no
@@ -569,4 +573,177 @@ int64_t orc_async_serial_run(int64_t m, int64_t n, const int64_t *col_ptr, const
             r[row_idx[p]] += d * val[p];
     }
     return changed;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Other smooth losses and separable regularisers (introduction: examples  */
+/* of partially separable functions and the table of three losses; the     */
+/* experiments on the SVM dual with box constraints and on L2-regularised  */
+/* logistic regression).                                                    */
+/*                                                                           */
+/*   f(x) = s * sum_j phi(z_j, y_j),   z = A x,                              */
+/*   phi: 0 square        0.5 (z - y)^2            phi'' <= 1               */
+/*        1 logistic      log(1 + exp(-y z))       phi'' <= 1/4             */
+/*        2 square hinge  0.5 max(0, 1 - y z)^2    phi'' <= 1 (y = +-1)     */
+/*   Omega_i(t) = l1 |t| + (l2/2) t^2 + c t + [lo <= t <= hi].               */
+/* f is partially separable with the omega of A, and its block Lipschitz   */
+/* constants are L_i = s * sup(phi'') * ||a_i||^2, so PCDM1 applies with the  */
+/* same beta and w = L.                                                      */
+/* ------------------------------------------------------------------------ */
+
+static double orc_phi(int loss, double z, double y)
+{
+    if (loss == 0)
+        return 0.5 * (z - y) * (z - y);
+    if (loss == 1) {
+        double t = -y * z; /* log(1 + e^t), evaluated without overflow */
+        return t > 0.0 ? t + log1p(exp(-t)) : log1p(exp(t));
+    }
+    {
+        double h = 1.0 - y * z;
+        return h > 0.0 ? 0.5 * h * h : 0.0;
+    }
+}
+
+/* d phi / d z */
+static double orc_dphi(int loss, double z, double y)
+{
+    if (loss == 0)
+        return z - y;
+    if (loss == 1) {
+        double t = y * z; /* -y / (1 + e^{t}) */
+        return t > 0.0 ? -y * exp(-t) / (1.0 + exp(-t)) : -y / (1.0 + exp(t));
+    }
+    {
+        double h = 1.0 - y * z;
+        return h > 0.0 ? -y * h : 0.0;
+    }
+}
+
+double orc_loss_value(int loss, double z, double y) { return orc_phi(loss, z, y); }
+double orc_loss_deriv(int loss, double z, double y) { return orc_dphi(loss, z, y); }
+
+double orc_loss_curvature_bound(int loss) { return loss == 1 ? 0.25 : 1.0; }
+
+/*
+ * The block minimiser for Omega_i: with v = x_i - g/(beta L_i) the update
+ * minimises (beta L_i / 2)(u - v)^2 + l1|u| + (l2/2)u^2 + c u over
+ * lo <= u <= hi.  Completing the square, the smooth part is
+ * ((beta L_i + l2)/2)(u - w)^2 + const with w = (beta L_i v - c)/(beta L_i + l2);
+ * the unconstrained minimiser of that plus l1|u| is soft(w, l1/(beta L_i + l2)),
+ * and for a convex function of one variable the minimiser over [lo, hi] is
+ * that point clipped to the interval.
+ */
+double orc_model_prox(double v, double bl, double l1, double l2, double c, double lo, double hi)
+{
+    double den = bl + l2;
+    double w = (bl * v - c) / den;
+    double u = orc_soft(w, l1 / den);
+    if (u < lo)
+        u = lo;
+    if (u > hi)
+        u = hi;
+    return u;
+}
+
+/* Omega_i summed over x (infinite outside the box). */
+double orc_model_omega(int64_t n, const double *x, double l1, double l2, double c, double lo, double hi)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (x[i] < lo || x[i] > hi)
+            return INFINITY;
+        acc += l1 * fabs(x[i]) + 0.5 * l2 * x[i] * x[i] + c * x[i];
+    }
+    return acc;
+}
+
+/* F(x) = s sum_j phi(z_j, y_j) + sum_i Omega_i(x_i) for z = A x. */
+double orc_model_objective(int64_t m, int64_t n, const double *z, const double *y, const double *x, int loss,
+                           double s, double l1, double l2, double c, double lo, double hi)
+{
+    double acc = 0.0;
+    for (int64_t j = 0; j < m; ++j)
+        acc += orc_phi(loss, z[j], y[j]);
+    return s * acc + orc_model_omega(n, x, l1, l2, c, lo, hi);
+}
+
+/*
+ * One synchronous PCDM1 step on the set S for the model above: every
+ * g_i = s * sum_p a_pi * phi'(z_{row p}, y_{row p}) from the same z = A x_k,
+ * then x_i <- prox (with beta L_i), then z += delta_i a_i in ascending i.
+ * L holds s * sup(phi'') * ||a_i||^2.  Returns the count of changed
+ * coordinates or -1 (duplicate / out-of-range index).
+ */
+int64_t orc_model_step_with_set(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
+                                const double *val, const double *L, const double *y, int loss, double s,
+                                double l1, double l2, double c, double lo, double hi, double beta, int64_t tau,
+                                const int64_t *S, double *x, double *z)
+{
+    int64_t *ids = (int64_t *)malloc((size_t)(tau > 0 ? tau : 1) * sizeof(int64_t));
+    double *delta = (double *)malloc((size_t)(tau > 0 ? tau : 1) * sizeof(double));
+    int64_t changed = 0;
+    (void)m;
+    if (!ids || !delta) {
+        free(ids);
+        free(delta);
+        return -1;
+    }
+    memcpy(ids, S, (size_t)tau * sizeof(int64_t));
+    qsort(ids, (size_t)tau, sizeof(int64_t), orc_cmp_i64);
+    for (int64_t t = 0; t < tau; ++t) {
+        if (ids[t] < 0 || ids[t] >= n || (t > 0 && ids[t] == ids[t - 1])) {
+            free(ids);
+            free(delta);
+            return -1;
+        }
+    }
+    for (int64_t t = 0; t < tau; ++t) {
+        int64_t i = ids[t];
+        double g = 0.0, bl = beta * L[i];
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            g += val[p] * orc_dphi(loss, z[row_idx[p]], y[row_idx[p]]);
+        g *= s;
+        delta[t] = orc_model_prox(x[i] - g / bl, bl, l1, l2, c, lo, hi) - x[i];
+    }
+    for (int64_t t = 0; t < tau; ++t) {
+        int64_t i = ids[t];
+        if (delta[t] == 0.0)
+            continue;
+        ++changed;
+        x[i] += delta[t];
+        for (int64_t p = col_ptr[i]; p < col_ptr[i + 1]; ++p)
+            z[row_idx[p]] += delta[t] * val[p];
+    }
+    free(ids);
+    free(delta);
+    return changed;
+}
+
+/* nsteps tau-nice steps k0 .. k0+nsteps-1 of the model (z = A x on entry). */
+int64_t orc_model_run(int64_t m, int64_t n, const int64_t *col_ptr, const int32_t *row_idx, const double *val,
+                      const double *L, const double *y, int loss, double s, double l1, double l2, double c,
+                      double lo, double hi, double beta, int64_t tau, uint64_t seed, int64_t k0, int64_t nsteps,
+                      double *x, double *z)
+{
+    int64_t *S = (int64_t *)malloc((size_t)(tau > 0 ? tau : 1) * sizeof(int64_t));
+    int64_t total = 0;
+    if (!S)
+        return -1;
+    for (int64_t k = k0; k < k0 + nsteps; ++k) {
+        int64_t cnt;
+        if (orc_sample_nice(seed, (uint64_t)k, tau, n, S) != 0) {
+            free(S);
+            return -1;
+        }
+        cnt = orc_model_step_with_set(m, n, col_ptr, row_idx, val, L, y, loss, s, l1, l2, c, lo, hi, beta, tau, S,
+                                      x, z);
+        if (cnt < 0) {
+            free(S);
+            return -1;
+        }
+        total += cnt;
+    }
+    free(S);
+    return total;
 }
