@@ -104,6 +104,10 @@ typedef struct pcdm_info {
     double expected_set_size;/* E|S_k| of the sampling (drop mask not included)   */
     int64_t mask_len;        /* slots covered by the drop mask (0 = none)         */
     int64_t narrow_below;    /* tau below which a slot gets a group of lanes      */
+    int32_t loss;            /* pcdm_loss of the model (PCDM_LOSS_SQUARE: LASSO)  */
+    int32_t reserved1;
+    double loss_scale;       /* model terms (see pcdm_model); lambda is l1       */
+    double l2, linear, lower, upper;
     int64_t async_picks;     /* picks made by pcdm_step_async so far              */
     int64_t async_processors;/* processors (lane groups) of its last launch       */
 } pcdm_info;
@@ -124,6 +128,55 @@ typedef struct pcdm_info {
  */
 int pcdm_create(const pcdm_csc *A, const double *b, double lambda, int64_t tau,
                 uint64_t seed, pcdm_problem **out);
+
+/*
+ * Other smooth losses and separable regularisers (introduction: partially
+ * separable f = sum_j loss_j with the table of three losses; numerical
+ * experiments: the SVM dual with box constraints, L2-regularised logistic
+ * regression):
+ *     F(x) = scale * sum_j phi_j((A x)_j) + sum_i Omega(x_i),
+ *     phi_j: PCDM_LOSS_SQUARE   0.5 (z - y_j)^2        (y = targets)
+ *            PCDM_LOSS_LOGISTIC log(1 + exp(-y_j z))   (y = labels +-1)
+ *            PCDM_LOSS_SQHINGE  0.5 max(0, 1 - y_j z)^2 (y = labels +-1)
+ *     Omega(t) = l1 |t| + (l2/2) t^2 + linear t + (0 if lower <= t <= upper
+ *                else +inf).
+ * f is partially separable with the omega of A; L_i = scale * sup(phi'')
+ * * ||a_i||^2 with sup(phi'') = 1, 1/4, 1; beta as for pcdm_create.  The
+ * block step is the minimiser of the model with Omega: clip(soft(w, t),
+ * lower, upper) with w = (x_i - (g_i + linear)/(beta L_i))/(1 + l2/(beta L_i))
+ * and t = (l1/(beta L_i))/(1 + l2/(beta L_i)).  Examples: LASSO {SQUARE, 1,
+ * lambda, 0, 0, -inf, inf}; elastic net (l2 > 0); non-negative LASSO (lower
+ * = 0); SVM dual of n examples (columns y_i a_i, rows the features, targets
+ * 0) {SQUARE, 1/(lambda n^2), 0, 0, -1/n, 0, 1}; L2 logistic
+ * sum_j log(1 + exp(-y_j a_j^T x)) + mu ||x||^2 {LOGISTIC, 1, 0, 2 mu, 0,
+ * -inf, inf}.  For the logistic and square-hinge losses the labels are
+ * multiplied into the stored values at create, and the maintained vector
+ * holds the margins y_j a_j^T x (r = A x - y for the square loss).
+ */
+typedef enum { PCDM_LOSS_SQUARE = 0, PCDM_LOSS_LOGISTIC = 1, PCDM_LOSS_SQHINGE = 2 } pcdm_loss;
+
+typedef struct pcdm_model {
+    int32_t loss;    /* pcdm_loss                                    */
+    int32_t reserved;
+    double scale;    /* > 0, finite                                  */
+    double l1, l2;   /* >= 0, finite                                 */
+    double linear;   /* finite                                       */
+    double lower;    /* <= 0 (may be -HUGE_VAL)                      */
+    double upper;    /* >= 0 (may be +HUGE_VAL)                      */
+} pcdm_model;
+
+/*
+ * Create a problem for a model (see above): y [m] float64 (targets or
+ * labels, host or device as A->on_device says).  As pcdm_create otherwise;
+ * PCDM_EINVAL also for labels other than +-1 and for model terms out of
+ * range.  pcdm_step and pcdm_objective (without dual_gap) serve every model;
+ * the duality gap, pcdm_grad_backward, pcdm_step_async and the batches are
+ * built for the LASSO only, and pcdm_set_rhs for the square loss only
+ * (PCDM_EINVAL otherwise).  Losses other than the square one run with one
+ * chunk per lane (chunks_per_lane = 1).
+ */
+int pcdm_create_model(const pcdm_csc *A, const double *y, const pcdm_model *model, int64_t tau,
+                      uint64_t seed, pcdm_problem **out);
 
 /* Free all device memory of the handle (synchronises the device). NULL is a no-op. */
 int pcdm_destroy(pcdm_problem *h);

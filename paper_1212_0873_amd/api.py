@@ -12,7 +12,7 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import (PCDM_BF16, PCDM_F32, PCDM_F64, PCDMError, check, load, pcdm_csc,  # noqa: F401
+from ._lib import (PCDM_BF16, PCDM_F32, PCDM_F64, PCDMError, check, load, pcdm_csc, pcdm_model,  # noqa: F401
                    pcdm_info)
 
 _NP_DTYPE = {np.dtype(np.float32): PCDM_F32, np.dtype(np.float64): PCDM_F64, np.dtype(np.uint16): PCDM_BF16}
@@ -49,7 +49,11 @@ class Problem:
     ``b`` is float64 in the same place.
     """
 
-    def __init__(self, A, b, lam: float, tau: int, seed: int = 0):
+    def __init__(self, A, b, lam: float, tau: int, seed: int = 0, model: Optional[dict] = None):
+        """``model`` (optional) selects another loss / regulariser
+        (``pcdm_create_model``): keys loss ('square', 'logistic', 'sqhinge'),
+        scale, l2, linear, lower, upper; ``lam`` is the l1 weight and ``b``
+        the targets or +-1 labels."""
         self._lib = load()
         self._h = ctypes.c_void_p()
         on_dev = not isinstance(A.values, np.ndarray)
@@ -73,8 +77,18 @@ class Problem:
         desc = pcdm_csc(int(A.m), int(A.n), nnz, _ptr(cp), _ptr(ri), _ptr(vals), dtype, int(on_dev))
         if on_dev:
             _torch().cuda.current_stream().synchronize()
-        check(self._lib.pcdm_create(ctypes.byref(desc), _ptr(bb), float(lam), int(tau),
-                                    int(seed) & (2**64 - 1), ctypes.byref(self._h)))
+        if model is None:
+            check(self._lib.pcdm_create(ctypes.byref(desc), _ptr(bb), float(lam), int(tau),
+                                        int(seed) & (2**64 - 1), ctypes.byref(self._h)))
+        else:
+            unknown = set(model) - {"loss", "scale", "l2", "linear", "lower", "upper"}
+            if unknown:
+                raise ValueError(f"unknown model keys {sorted(unknown)}")
+            mdl = pcdm_model(LOSSES[model.get("loss", "square")], 0, float(model.get("scale", 1.0)), float(lam),
+                             float(model.get("l2", 0.0)), float(model.get("linear", 0.0)),
+                             float(model.get("lower", -np.inf)), float(model.get("upper", np.inf)))
+            check(self._lib.pcdm_create_model(ctypes.byref(desc), _ptr(bb), ctypes.byref(mdl), int(tau),
+                                              int(seed) & (2**64 - 1), ctypes.byref(self._h)))
         self._keep = None
         self.m, self.n, self.dtype = int(A.m), int(A.n), dtype
 
@@ -245,6 +259,7 @@ def sample(seed: int, k: int, tau: int, n: int):
 
 
 SAMPLINGS = {"nice": 0, "independent": 1, "binomial": 2}
+LOSSES = {"square": 0, "logistic": 1, "sqhinge": 2}
 
 
 def sample_draw(sampling: str, seed: int, k: int, tau: int, n: int, pb: float = 1.0):

@@ -48,7 +48,7 @@ k_batch_gather(char *__restrict__ seg, const BatchInst *__restrict__ desc, const
         const SlotDraw sd = slot_draw_for(plan_nice(), d.seed, d.k);
         gather_tile<V, G, C>(seg + d.rec_base, d.lay, r + d.row_base, xm + d.col_base, id_slot + d.slot_base,
                              delta_slot + d.slot_base, key, sd, tl, (t - d.step_tile0) * 64, d.tau, d.inv_beta,
-                             d.lam, nz);
+                             prox_lasso(d.lam), nz);
     }
     const uint64_t tot = block_sum_u64(nz, s_red);
     if (threadIdx.x == 0 && tot)

@@ -81,7 +81,8 @@ enum : uint32_t {
     ERR_ROW = 4u,      // row index out of range
     ERR_DUP = 8u,      // repeated row in a column
     ERR_NONFINITE = 16u,
-    ERR_ZEROCOL = 32u  // column with L_i = 0
+    ERR_ZEROCOL = 32u,  // column with L_i = 0
+    ERR_LABEL = 64u     // label other than +-1 (logistic / square hinge)
 };
 
 template <typename V> struct ValT;
@@ -159,6 +160,72 @@ template <> struct Chunk4<bf16s> {
 template <typename T> __device__ __forceinline__ T soft_threshold(T u, T c)
 {
     return u > c ? u - c : (u < -c ? u + c : T(0));
+}
+
+// Smooth losses f = s * sum_j phi(m_j) (introduction, table of three losses).
+// For the logistic and square-hinge losses the labels are folded into the
+// stored values (row j times y_j), so the maintained vector holds the
+// margins m_j = y_j a_j^T x and phi needs no label: logistic
+// log(1 + exp(-m)), square hinge 0.5 max(0, 1 - m)^2.  The square loss keeps
+// r = A x - b and phi(r) = 0.5 r^2.  dphi is d phi / d m (or d r).
+enum : int { kLossSquare = 0, kLossLogistic = 1, kLossSqHinge = 2 };
+
+template <int Loss, typename T> __device__ __forceinline__ T dphi(T m)
+{
+    if constexpr (Loss == kLossLogistic) {
+        return T(-1) / (T(1) + exp(m));
+    } else if constexpr (Loss == kLossSqHinge) {
+        const T h = T(1) - m;
+        return h > T(0) ? -h : T(0);
+    } else {
+        return m;
+    }
+}
+
+template <int Loss> __device__ __forceinline__ double phi64(double m)
+{
+    if constexpr (Loss == kLossLogistic) {
+        return m < 0.0 ? -m + log1p(exp(m)) : log1p(exp(-m));
+    } else if constexpr (Loss == kLossSqHinge) {
+        const double h = 1.0 - m;
+        return h > 0.0 ? 0.5 * h * h : 0.0;
+    } else {
+        return 0.5 * m * m;
+    }
+}
+
+// Separable regulariser Omega_i(t) = l1|t| + (l2/2)t^2 + c t + [lo <= t <= hi]
+// and the scale s of the loss (partial derivatives are s * a_i^T phi'(.)).
+struct ProxParams {
+    double l1, l2, c, lo, hi, gscale;
+};
+
+__host__ __device__ inline ProxParams prox_lasso(double lam)
+{
+    ProxParams p;
+    p.l1 = lam;
+    p.l2 = 0.0;
+    p.c = 0.0;
+    p.lo = -HUGE_VAL;
+    p.hi = HUGE_VAL;
+    p.gscale = 1.0;
+    return p;
+}
+
+// Block minimiser of g t + (beta L/2) t^2 + Omega(x + t), returned as the new
+// x (scale = 1/(beta L)): for u = x + t the smooth part is
+// ((beta L + l2)/2)(u - w)^2 + const, w = (x - (g + c) scale)/(1 + l2 scale);
+// l1|u| makes it a soft threshold at l1 scale/(1 + l2 scale), and the box a
+// clip (the minimiser of a convex function of one variable over an interval).
+// With l2 = c = 0 this is the LASSO step soft(x - g scale, l1 scale).
+__device__ __forceinline__ double model_prox(double xi, double g, double scale, const ProxParams &pp)
+{
+    double u;
+    if (pp.l2 == 0.0 && pp.c == 0.0)
+        u = soft_threshold<double>(xi - g * scale, pp.l1 * scale);
+    else
+        u = soft_threshold<double>(xi - (g + pp.c) * scale, pp.l1 * scale) / (1.0 + pp.l2 * scale);
+    return fmin(fmax(u, pp.lo), pp.hi);
 }
 
 template <typename T> __device__ __forceinline__ void atomic_add_hw(T *p, T v)
@@ -262,13 +329,13 @@ __device__ __forceinline__ void tile_entries(const char *__restrict__ seg, const
 // `key`.  Slot j takes i = pi_k(j), g_i = a_i^T r (working precision T) and
 // the damped soft-threshold update of x_i in float64; records (i, delta_i) in
 // slot j and writes x_i (record and mirror).  Pointers are the problem's own.
-template <typename V, int G, int C>
+template <typename V, int G, int C, int Loss = kLossSquare>
 __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout &lay,
                                             const typename ValT<V>::T *__restrict__ r, double *__restrict__ xm,
                                             int32_t *__restrict__ id_slot,
                                             typename ValT<V>::T *__restrict__ delta_slot, const NiceKey &key,
                                             const SlotDraw &sd, const TileLanes<G> &tl, int64_t base, int64_t tau,
-                                            double inv_beta, double lam, uint64_t &nz)
+                                            double inv_beta, const ProxParams &pp, uint64_t &nz)
 {
     using T = typename ValT<V>::T;
     const int64_t slot = base + tl.lane;
@@ -325,7 +392,7 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
                 if (4 * (tl.gl + G * c) < qdp[qq]) {
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
-                        acc[qq] += v[qq][c][t] * load_row(r, rw[qq][c][t]);
+                        acc[qq] += v[qq][c][t] * dphi<Loss>(load_row(r, rw[qq][c][t]));
                 }
             }
         }
@@ -338,7 +405,7 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
                 Chunk4<V>::load(rows, qdp[qq], e, rr, vv);
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    acc[qq] += vv[t] * load_row(r, rr[t]);
+                    acc[qq] += vv[t] * dphi<Loss>(load_row(r, rr[t]));
             }
         }
 #pragma unroll
@@ -351,8 +418,7 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
         }
     }
     if (act) {
-        const double scale = il * inv_beta;  // 1 / (beta L_i)
-        const double xn = soft_threshold<double>(xi - (double)mine * scale, lam * scale);
+        const double xn = model_prox(xi, (double)mine * pp.gscale, il * inv_beta, pp);  // il * inv_beta = 1/(beta L_i)
         const double d = live ? xn - xi : 0.0;
         id_slot[slot] = (int32_t)i;
         delta_slot[slot] = (T)d;
@@ -389,12 +455,12 @@ __device__ __forceinline__ void scatter_tile(const char *__restrict__ seg, const
 }
 
 // Phase 1 of step k over all tiles of one problem.
-template <typename V, int G, int C>
+template <typename V, int G, int C, int Loss = kLossSquare>
 __global__ void __launch_bounds__(kBlock)
 k_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
          double *__restrict__ xm, int32_t *__restrict__ id_slot, typename ValT<V>::T *__restrict__ delta_slot,
          const Ctrl *__restrict__ ctrl, uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau,
-         uint32_t n, double inv_beta, double lam, SlotPlan plan)
+         uint32_t n, double inv_beta, ProxParams pp, SlotPlan plan)
 {
     __shared__ uint32_t s_keys[kNiceRounds];
     __shared__ uint64_t s_red[kBlock / 64];
@@ -404,7 +470,7 @@ k_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restri
     const TileLanes<G> tl;
     uint64_t nz = 0;
     for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64)
-        gather_tile<V, G, C>(seg, lay, r, xm, id_slot, delta_slot, key, sd, tl, base, tau, inv_beta, lam, nz);
+        gather_tile<V, G, C, Loss>(seg, lay, r, xm, id_slot, delta_slot, key, sd, tl, base, tau, inv_beta, pp, nz);
     const uint64_t tot = block_sum_u64(nz, s_red);
     if (threadIdx.x == 0 && tot)
         nz_part[blockIdx.x] += tot;
@@ -451,7 +517,7 @@ template <typename T, int Mode> __device__ __forceinline__ T load_r(const T *bas
         return load_row(base, row);
 }
 
-template <typename V, int G, int C, int Fresh = kReadCached>
+template <typename V, int G, int C, int Fresh = kReadCached, int Loss = kLossSquare>
 __device__ __forceinline__ typename ValT<V>::T lane_dot(const char *rows, int32_t dp, int gl,
                                                         const typename ValT<V>::T *r)
 {
@@ -477,7 +543,7 @@ __device__ __forceinline__ typename ValT<V>::T lane_dot(const char *rows, int32_
         if (4 * (gl + G * c) < dp) {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-                acc += v[c][t] * load_r<T, Fresh>(r, rw[c][t]);
+                acc += v[c][t] * dphi<Loss>(load_r<T, Fresh>(r, rw[c][t]));
         }
     }
     for (int e = 4 * (gl + G * C); e < dp; e += 4 * G) {
@@ -486,18 +552,18 @@ __device__ __forceinline__ typename ValT<V>::T lane_dot(const char *rows, int32_
         Chunk4<V>::load(rows, dp, e, rr, vv);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-            acc += vv[t] * load_r<T, Fresh>(r, rr[t]);
+            acc += vv[t] * dphi<Loss>(load_r<T, Fresh>(r, rr[t]));
     }
     return acc;
 }
 
-template <typename V, int G, int C>
+template <typename V, int G, int C, int Loss>
 __device__ __forceinline__ void gather_slot_narrow(char *__restrict__ seg, const Layout &lay,
                                                    const typename ValT<V>::T *__restrict__ r, double *__restrict__ xm,
                                                    int32_t *__restrict__ id_slot,
                                                    typename ValT<V>::T *__restrict__ delta_slot, const NiceKey &key,
                                                    const SlotDraw &sd, int gl, int leader, int64_t slot,
-                                                   int64_t tau, double inv_beta, double lam, uint64_t &nz)
+                                                   int64_t tau, double inv_beta, const ProxParams &pp, uint64_t &nz)
 {
     using T = typename ValT<V>::T;
     const bool act = slot < tau;  // the same for the whole group
@@ -517,10 +583,9 @@ __device__ __forceinline__ void gather_slot_narrow(char *__restrict__ seg, const
     }
     off = __shfl(off, leader);
     dp = __shfl(dp, leader);
-    const T g = group_sum<G>(lane_dot<V, G, C>(seg + off + kHeader, dp, gl, r));
+    const T g = group_sum<G>(lane_dot<V, G, C, kReadCached, Loss>(seg + off + kHeader, dp, gl, r));
     if (act && gl == 0) {
-        const double scale = il * inv_beta;
-        const double xn = soft_threshold<double>(xi - (double)g * scale, lam * scale);
+        const double xn = model_prox(xi, (double)g * pp.gscale, il * inv_beta, pp);
         const double d = live ? xn - xi : 0.0;
         id_slot[slot] = (int32_t)i;
         delta_slot[slot] = (T)d;
@@ -532,12 +597,12 @@ __device__ __forceinline__ void gather_slot_narrow(char *__restrict__ seg, const
     }
 }
 
-template <typename V, int G, int C>
+template <typename V, int G, int C, int Loss = kLossSquare>
 __global__ void __launch_bounds__(kBlock)
 k_gather_narrow(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
                 double *__restrict__ xm, int32_t *__restrict__ id_slot, typename ValT<V>::T *__restrict__ delta_slot,
                 const Ctrl *__restrict__ ctrl, uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau,
-                uint32_t n, double inv_beta, double lam, SlotPlan plan)
+                uint32_t n, double inv_beta, ProxParams pp, SlotPlan plan)
 {
     __shared__ uint32_t s_keys[kNiceRounds];
     __shared__ uint64_t s_red[kBlock / 64];
@@ -550,8 +615,8 @@ k_gather_narrow(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *_
     const int leader = lane & ~(G - 1);
     uint64_t nz = 0;
     for (int64_t base = wave_global_id() * SPW; base < tau; base += wave_count() * SPW)
-        gather_slot_narrow<V, G, C>(seg, lay, r, xm, id_slot, delta_slot, key, sd, gl, leader, base + lane / G, tau,
-                                    inv_beta, lam, nz);
+        gather_slot_narrow<V, G, C, Loss>(seg, lay, r, xm, id_slot, delta_slot, key, sd, gl, leader, base + lane / G,
+                                          tau, inv_beta, pp, nz);
     const uint64_t tot = block_sum_u64(nz, s_red);
     if (threadIdx.x == 0 && tot)
         nz_part[blockIdx.x] += tot;
@@ -881,6 +946,69 @@ k_final(const double *__restrict__ part, int nparts, int ncomp, int mode, double
         a = mode ? block_max_f64(a, lds) : block_sum_f64(a, lds);
         if (threadIdx.x == 0)
             out[c] = a;
+    }
+}
+
+// part[2*blk + {0,1}] = partial sums of phi(r64_j) over rows and of
+// Omega(x_i) over columns (outside the box: +inf).
+template <int Loss>
+__global__ void __launch_bounds__(kBlock)
+k_model_partials(const double *__restrict__ r64, int64_t m, const double *__restrict__ xm, int64_t n,
+                 ProxParams pp, double *__restrict__ part)
+{
+    __shared__ double lds[kBlock];
+    double fl = 0.0, om = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m; j += stride)
+        fl += phi64<Loss>(r64[j]);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const double t = xm[i];
+        om += (t < pp.lo || t > pp.hi) ? HUGE_VAL : pp.l1 * fabs(t) + 0.5 * pp.l2 * t * t + pp.c * t;
+    }
+    fl = block_sum_f64(fl, lds);
+    om = block_sum_f64(om, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 0] = fl;
+        part[2 * blockIdx.x + 1] = om;
+    }
+}
+
+// Fold labels into the stored values: every entry of row j (padding
+// included) times y[j]; flags labels other than +-1.
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_fold_labels(char *__restrict__ seg, Layout lay, int64_t n, const double *__restrict__ y, Ctrl *__restrict__ ctrl)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        int64_t off;
+        int32_t dp;
+        locate<V>(lay, i, off, dp);
+        const int32_t *rows = reinterpret_cast<const int32_t *>(seg + off + kHeader);
+        V *vals = reinterpret_cast<V *>(seg + off + kHeader + 4 * (int64_t)dp);
+        for (int32_t e = 0; e < dp; ++e) {
+            const double lab = y[rows[e]];
+            if (lab == -1.0) {
+                if constexpr (sizeof(V) == 2)
+                    vals[e].bits ^= 0x8000u;
+                else
+                    vals[e] = -vals[e];
+            } else if (lab != 1.0) {
+                atomicOr(&ctrl->err, (uint32_t)ERR_LABEL);
+            }
+        }
+    }
+}
+
+// 1/L_i in the record headers times `factor`.
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_scale_invl(char *__restrict__ seg, Layout lay, int64_t n, double factor)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        int64_t off;
+        int32_t dp;
+        locate<V>(lay, i, off, dp);
+        reinterpret_cast<double *>(seg + off)[1] *= factor;
     }
 }
 

@@ -126,6 +126,10 @@ struct pcdm_problem {
     uint32_t *claim = nullptr; // [n] claim stamps for independent picks
     int64_t claim_base = 0;    // step at which claim was last zeroed
 
+    // model: f = lscale * sum_j phi(.), Omega_i = lambda|t| + (l2/2)t^2 + lin t + box
+    int loss = kLossSquare;
+    double lscale = 1.0, l2 = 0.0, lin = 0.0, lo = -HUGE_VAL, hi = HUGE_VAL;
+
     // asynchronous variant
     int cus = 0;
     int async_reads = -1;      // kReadCached / kReadAcquire / kReadAtomic, -1 = by processor count
@@ -243,6 +247,26 @@ SlotPlan slot_plan(const pcdm_problem *P)
     return p;
 }
 
+// The LASSO of the paper's experiments (square loss, l1 only): the paths
+// that are specific to it (duality gap, adjoint, batches, asynchronous
+// variant) require it.
+bool is_lasso(const pcdm_problem *P)
+{
+    return P->loss == kLossSquare && P->lscale == 1.0 && P->l2 == 0.0 && P->lin == 0.0 && P->lo == -HUGE_VAL &&
+           P->hi == HUGE_VAL;
+}
+
+ProxParams prox_params(const pcdm_problem *P)
+{
+    ProxParams p = prox_lasso(P->lambda);
+    p.l2 = P->l2;
+    p.c = P->lin;
+    p.lo = P->lo;
+    p.hi = P->hi;
+    p.gscale = P->lscale;
+    return p;
+}
+
 // Zero the claim stamps and restart their numbering at step k (a fill
 // kernel, so the call is safe inside a captured stream).
 void reset_claims(pcdm_problem *P, int64_t k, hipStream_t s)
@@ -276,8 +300,10 @@ void pick_schedule(pcdm_problem *P)
     }
 }
 
-bool schedule_supported(int g, int c)
+bool schedule_supported(int g, int c, int loss = kLossSquare)
 {
+    if (loss != kLossSquare && c != 1)
+        return false;  // other losses are built with one chunk per lane
     switch (g * 16 + c) {
     case 1 * 16 + 1: case 1 * 16 + 2: case 1 * 16 + 4: case 2 * 16 + 1: case 2 * 16 + 2:
     case 2 * 16 + 4: case 4 * 16 + 1: case 4 * 16 + 2: case 8 * 16 + 1: case 8 * 16 + 2:
@@ -364,15 +390,15 @@ int ensure_slots(pcdm_problem *P, int64_t tau)
 template <typename V> struct Ops {
     using T = typename ValT<V>::T;
 
-    template <int G, int C> static void launch_step(pcdm_problem *P, hipStream_t s)
+    template <int G, int C, int Loss> static void launch_step(pcdm_problem *P, hipStream_t s)
     {
         if (P->tau < P->narrow_below) {
             // one slot per group of G lanes
             const int grid = grid_for(P->tau * G, kBlock, P->nblk_max);
             hipEvent_t t0 = clock_start(P, s);
-            hipLaunchKernelGGL((k_gather_narrow<V, G, C>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
+            hipLaunchKernelGGL((k_gather_narrow<V, G, C, Loss>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
                                (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part, P->seed,
-                               P->tau, (uint32_t)P->n, 1.0 / P->beta, P->lambda, slot_plan(P));
+                               P->tau, (uint32_t)P->n, 1.0 / P->beta, prox_params(P), slot_plan(P));
             clock_stop(P, CLK_GATHER, t0, s);
             hipEvent_t t1 = clock_start(P, s);
             hipLaunchKernelGGL((k_scatter_narrow<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg,
@@ -383,9 +409,9 @@ template <typename V> struct Ops {
         }
         const int grid = grid_for(P->tau, kBlock, P->nblk_max);  // one slot per thread per tile
         hipEvent_t t0 = clock_start(P, s);
-        hipLaunchKernelGGL((k_gather<V, G, C>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
+        hipLaunchKernelGGL((k_gather<V, G, C, Loss>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay,
                            (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part,
-                           P->seed, P->tau, (uint32_t)P->n, 1.0 / P->beta, P->lambda, slot_plan(P));
+                           P->seed, P->tau, (uint32_t)P->n, 1.0 / P->beta, prox_params(P), slot_plan(P));
         clock_stop(P, CLK_GATHER, t0, s);
         hipEvent_t t1 = clock_start(P, s);
         hipLaunchKernelGGL((k_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
@@ -464,23 +490,72 @@ template <typename V> struct Ops {
 
     static int step_once(pcdm_problem *P, hipStream_t s)
     {
-        switch (P->lanes * 16 + P->chunks) {
-        case 1 * 16 + 1: launch_step<1, 1>(P, s); break;
-        case 1 * 16 + 2: launch_step<1, 2>(P, s); break;
-        case 1 * 16 + 4: launch_step<1, 4>(P, s); break;
-        case 2 * 16 + 1: launch_step<2, 1>(P, s); break;
-        case 2 * 16 + 2: launch_step<2, 2>(P, s); break;
-        case 2 * 16 + 4: launch_step<2, 4>(P, s); break;
-        case 4 * 16 + 1: launch_step<4, 1>(P, s); break;
-        case 4 * 16 + 2: launch_step<4, 2>(P, s); break;
-        case 8 * 16 + 1: launch_step<8, 1>(P, s); break;
-        case 8 * 16 + 2: launch_step<8, 2>(P, s); break;
-        case 16 * 16 + 1: launch_step<16, 1>(P, s); break;
-        case 32 * 16 + 1: launch_step<32, 1>(P, s); break;
-        case 64 * 16 + 1: launch_step<64, 1>(P, s); break;
-        default: return fail(PCDM_EINVAL, "unsupported (lanes_per_column, chunks_per_lane) pair");
+        switch (P->loss) {
+        case kLossLogistic: return step_loss<kLossLogistic>(P, s);
+        case kLossSqHinge: return step_loss<kLossSqHinge>(P, s);
+        default: return step_loss<kLossSquare>(P, s);
         }
-        return PCDM_OK;
+    }
+
+    template <int Loss> static int step_loss(pcdm_problem *P, hipStream_t s)
+    {
+        // the square loss has every schedule; the others one chunk per lane
+        constexpr bool all = Loss == kLossSquare;
+        switch (P->lanes * 16 + P->chunks) {
+        case 1 * 16 + 1: launch_step<1, 1, Loss>(P, s); return PCDM_OK;
+        case 2 * 16 + 1: launch_step<2, 1, Loss>(P, s); return PCDM_OK;
+        case 4 * 16 + 1: launch_step<4, 1, Loss>(P, s); return PCDM_OK;
+        case 8 * 16 + 1: launch_step<8, 1, Loss>(P, s); return PCDM_OK;
+        case 16 * 16 + 1: launch_step<16, 1, Loss>(P, s); return PCDM_OK;
+        case 32 * 16 + 1: launch_step<32, 1, Loss>(P, s); return PCDM_OK;
+        case 64 * 16 + 1: launch_step<64, 1, Loss>(P, s); return PCDM_OK;
+        default: break;
+        }
+        if constexpr (all) {
+            switch (P->lanes * 16 + P->chunks) {
+            case 1 * 16 + 2: launch_step<1, 2, Loss>(P, s); return PCDM_OK;
+            case 1 * 16 + 4: launch_step<1, 4, Loss>(P, s); return PCDM_OK;
+            case 2 * 16 + 2: launch_step<2, 2, Loss>(P, s); return PCDM_OK;
+            case 2 * 16 + 4: launch_step<2, 4, Loss>(P, s); return PCDM_OK;
+            case 4 * 16 + 2: launch_step<4, 2, Loss>(P, s); return PCDM_OK;
+            case 8 * 16 + 2: launch_step<8, 2, Loss>(P, s); return PCDM_OK;
+            default: break;
+            }
+        }
+        return fail(PCDM_EINVAL, "unsupported (lanes_per_column, chunks_per_lane) pair");
+    }
+
+    // F = lscale * sum_j phi(r64_j) + sum_i Omega(x_i) into ctrl->scal[0..1]
+    // (r64 already A x - b).
+    static void model_sums(pcdm_problem *P, hipStream_t s)
+    {
+        const ProxParams pp = prox_params(P);
+        switch (P->loss) {
+        case kLossLogistic:
+            hipLaunchKernelGGL(k_model_partials<kLossLogistic>, dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                               (const double *)P->r64, P->m, (const double *)P->x, P->n, pp, P->part);
+            break;
+        case kLossSqHinge:
+            hipLaunchKernelGGL(k_model_partials<kLossSqHinge>, dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                               (const double *)P->r64, P->m, (const double *)P->x, P->n, pp, P->part);
+            break;
+        default:
+            hipLaunchKernelGGL(k_model_partials<kLossSquare>, dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                               (const double *)P->r64, P->m, (const double *)P->x, P->n, pp, P->part);
+            break;
+        }
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part, kReduceBlocks, 2, 0,
+                           P->ctrl->scal);
+    }
+
+    static void fold_and_scale(pcdm_problem *P, const double *labels, double invl_factor, hipStream_t s)
+    {
+        const int gn = grid_for(P->n, kBlock, P->nblk_max);
+        if (labels)
+            hipLaunchKernelGGL((k_fold_labels<V>), dim3(gn), dim3(kBlock), 0, s, P->seg, P->lay, P->n, labels,
+                               P->ctrl);
+        if (invl_factor != 1.0)
+            hipLaunchKernelGGL((k_scale_invl<V>), dim3(gn), dim3(kBlock), 0, s, P->seg, P->lay, P->n, invl_factor);
     }
 
     // r64 = A x - b in float64.
@@ -629,11 +704,12 @@ std::string describe_err(uint32_t e)
     if (e & ERR_DUP) out += "repeated row index within a column; ";
     if (e & ERR_NONFINITE) out += "non-finite value; ";
     if (e & ERR_ZEROCOL) out += "column with only zero values (L_i = 0); ";
+    if (e & ERR_LABEL) out += "label other than +1 / -1; ";
     return out;
 }
 
 int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, uint64_t seed,
-                pcdm_problem **out)
+                const pcdm_model *model, pcdm_problem **out)
 {
     if (!out)
         return fail(PCDM_EINVAL, "out is NULL");
@@ -777,6 +853,32 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
         P->omega = hc.imax;
     }
 
+    if (model) {
+        // labels folded into the values, L_i scaled by s * sup(phi'')
+        P->loss = model->loss;
+        P->lscale = model->scale;
+        P->l2 = model->l2;
+        P->lin = model->linear;
+        P->lo = model->lower;
+        P->hi = model->upper;
+        const double curv = P->loss == kLossLogistic ? 0.25 : 1.0;
+        const double *labels = P->loss != kLossSquare ? P->b64 : nullptr;
+        PCDM_TRY(dispatch(P->dtype, [&](auto ops) {
+            decltype(ops)::fold_and_scale(P, labels, 1.0 / (P->lscale * curv), s);
+            return PCDM_OK;
+        }));
+        PCDM_TRY(check_launch("model set-up"));
+        Ctrl hc;
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(&hc, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        if (hc.err & ERR_LABEL)
+            return fail(PCDM_EINVAL, "labels of the logistic / square-hinge loss must be +1 or -1");
+        if (labels) {
+            const int gm = grid_for(A->m, kBlock, P->nblk_max);
+            hipLaunchKernelGGL((k_fill<double>), dim3(gm), dim3(kBlock), 0, s, P->b64, 0.0, P->m);
+        }
+    }
+
     pick_schedule(P);
     P->lanes_auto = 1;
     compute_beta(P);
@@ -814,7 +916,34 @@ int pcdm_create(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
 {
     t_err.clear();
     try {
-        return create_impl(A, b, lambda, tau, seed, out);
+        return create_impl(A, b, lambda, tau, seed, nullptr, out);
+    } catch (const std::exception &e) {
+        return fail(PCDM_EDEVICE, std::string("exception: ") + e.what());
+    } catch (...) {
+        return fail(PCDM_EDEVICE, "unknown exception");
+    }
+}
+
+int pcdm_create_model(const pcdm_csc *A, const double *y, const pcdm_model *model, int64_t tau, uint64_t seed,
+                      pcdm_problem **out)
+{
+    t_err.clear();
+    if (out)
+        *out = nullptr;
+    if (!model)
+        return fail(PCDM_EINVAL, "model is NULL");
+    if (model->loss < kLossSquare || model->loss > kLossSqHinge)
+        return fail(PCDM_EINVAL, "loss must be PCDM_LOSS_SQUARE, PCDM_LOSS_LOGISTIC or PCDM_LOSS_SQHINGE");
+    if (!(model->scale > 0.0) || !std::isfinite(model->scale))
+        return fail(PCDM_EINVAL, "scale must be finite and > 0");
+    if (!(model->l1 >= 0.0) || !std::isfinite(model->l1) || !(model->l2 >= 0.0) || !std::isfinite(model->l2))
+        return fail(PCDM_EINVAL, "l1 and l2 must be finite and >= 0");
+    if (!std::isfinite(model->linear))
+        return fail(PCDM_EINVAL, "linear must be finite");
+    if (!(model->lower <= 0.0) || !(model->upper >= 0.0))
+        return fail(PCDM_EINVAL, "need lower <= 0 <= upper (x starts at 0)");
+    try {
+        return create_impl(A, y, model->l1, tau, seed, model, out);
     } catch (const std::exception &e) {
         return fail(PCDM_EDEVICE, std::string("exception: ") + e.what());
     } catch (...) {
@@ -874,8 +1003,8 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             h->lanes_auto = 1;
         } else {
             const int g = k == "lanes_per_column" ? v : h->lanes;
-            const int c = k == "chunks_per_lane" ? v : (schedule_supported(v, h->chunks) ? h->chunks : 1);
-            if (!schedule_supported(g, c))
+            const int c = k == "chunks_per_lane" ? v : (schedule_supported(v, h->chunks, h->loss) ? h->chunks : 1);
+            if (!schedule_supported(g, c, h->loss))
                 return fail(PCDM_EINVAL, "unsupported (lanes_per_column, chunks_per_lane) pair");
             h->lanes = g;
             h->chunks = c;
@@ -978,6 +1107,12 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->expected_set_size = expected_set_size(h);
     out->mask_len = h->mask_len;
     out->narrow_below = h->narrow_below;
+    out->loss = h->loss;
+    out->loss_scale = h->lscale;
+    out->l2 = h->l2;
+    out->linear = h->lin;
+    out->lower = h->lo;
+    out->upper = h->hi;
     out->async_picks = h->async_picks;
     out->async_processors = h->async_procs_last;
     return PCDM_OK;
@@ -1006,6 +1141,8 @@ int pcdm_step_async(pcdm_problem *h, int64_t picks, void *stream)
 {
     if (!h)
         return fail(PCDM_EINVAL, "NULL handle");
+    if (!is_lasso(h))
+        return fail(PCDM_EINVAL, "the asynchronous variant is built for the LASSO (square loss, l1 term)");
     if (picks < 0)
         return fail(PCDM_EINVAL, "picks must be >= 0");
     if (picks == 0)
@@ -1029,6 +1166,21 @@ int pcdm_objective(pcdm_problem *h, double *F, double *dual_gap, void *stream)
         return fail(PCDM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     h->last_stream = s;
+    if (!is_lasso(h)) {
+        if (dual_gap)
+            return fail(PCDM_EINVAL, "the duality gap is computed for the LASSO only (square loss, l1 term)");
+        PCDM_TRY(dispatch(h->dtype, [&](auto ops) {
+            decltype(ops)::residual64(h, s);
+            decltype(ops)::model_sums(h, s);
+            return PCDM_OK;
+        }));
+        PCDM_TRY(check_launch("pcdm_objective"));
+        double sc2[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(sc2, h->ctrl->scal, sizeof(sc2), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *F = h->lscale * sc2[0] + sc2[1];
+        return PCDM_OK;
+    }
     PCDM_TRY(dispatch(h->dtype, [&](auto ops) {
         decltype(ops)::residual64(h, s);
         decltype(ops)::sums(h, s);
@@ -1166,6 +1318,8 @@ int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db, doub
 {
     if (!h || !dL_dx || !dL_db || !dL_dlambda)
         return fail(PCDM_EINVAL, "NULL argument");
+    if (!is_lasso(h))
+        return fail(PCDM_EINVAL, "the adjoint is built for the LASSO (square loss, l1 term)");
     hipStream_t s = (hipStream_t)stream;
     h->last_stream = s;
     const int64_t n = h->n, m = h->m;
@@ -1282,6 +1436,8 @@ int pcdm_set_rhs(pcdm_problem *h, const double *b, int32_t on_device, void *stre
 {
     if (!h || !b)
         return fail(PCDM_EINVAL, "NULL argument");
+    if (h->loss != kLossSquare)
+        return fail(PCDM_EINVAL, "labels are folded into the stored values: create a new problem to change them");
     hipStream_t s = (hipStream_t)stream;
     h->last_stream = s;
     HIP_TRY(hipMemcpyAsync(h->b64, b, (size_t)h->m * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
@@ -1337,6 +1493,8 @@ int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream)
     const int64_t widths[2] = {0, INT64_MAX};
     for (int64_t nb : widths) {
         for (const auto &c : cand) {
+            if (!schedule_supported(c[0], c[1], h->loss))
+                continue;
             h->lanes = c[0];
             h->chunks = c[1];
             h->narrow_below = nb;
