@@ -385,6 +385,82 @@ def run_async(args) -> int:
     return 0
 
 
+def run_models(args) -> int:
+    """Other losses on instances shaped like the paper's last two experiments:
+    L2-regularised logistic regression (sum_j log(1 + exp(-y_j a_j^T x)) +
+    ||x||^2, i.e. l2 = 2) on 19,264,097 examples x 29,890,095 features with 19
+    nonzeros per feature (5.7e8 nonzeros, written on the device; labels the
+    signs of a planted linear model plus noise), reported as F(x0)/F(x_k) and
+    seconds per epoch as in the paper's table; and the SVM dual (box [0, 1])
+    on 677,399 examples x 47,236 features with 73 nonzeros per example."""
+    import numpy as np
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import CSC, biggen, random_csc
+
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC, "mode": "models", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic"}
+    m_ex, n_feat, d = 19_264_097, 29_890_095, 19
+    t0 = time.time()
+    A, b, _ = biggen.device_instance(m_ex, n_feat, d, 3_000_000, 0.1, seed=0, dtype=args.dtype)
+    y = torch.where(b >= 0, 1.0, -1.0).to(torch.float64)
+    del b
+    torch.cuda.synchronize()
+    print(f"[bench] logistic instance written in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    res = {}
+    for tau in (65536, 1 << 20):
+        with pc.Problem(A, y, 0.0, tau, seed=0, model=dict(loss="logistic", l2=2.0)) as p:
+            spe = -(-n_feat // tau)
+            F0, _ = p.objective()
+            rows = []
+            for epoch in range(1, 4):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                p.step(spe)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                F, _ = p.objective()
+                rows.append({"epoch": epoch, "F0_over_F": F0 / F, "seconds": dt, "updates_per_s": spe * tau / dt})
+            res[str(tau)] = {"beta": p.info()["beta"], "omega": p.info()["omega"], "F0": F0, "epochs": rows}
+            print(f"[bench] logistic tau={tau}: {res[str(tau)]}", file=sys.stderr, flush=True)
+    out["logistic_l2"] = {"workload": "logistic_19264097x29890095_d19", "nnz": n_feat * d, "tau": res}
+    del A, y
+    torch.cuda.empty_cache()
+
+    rng = np.random.default_rng(0)
+    d_feat, n_ex, per = 47_236, 677_399, 73
+    X = random_csc(d_feat, n_ex, per, rng, normalize=False, dtype="f64")
+    w = rng.standard_normal(d_feat)
+    import scipy.sparse as sp
+    S = sp.csc_matrix((X.values, X.row_idx, X.col_ptr), shape=(d_feat, n_ex))
+    lab = np.where(S.T @ w + 0.5 * rng.standard_normal(n_ex) >= 0, 1.0, -1.0)
+    vals = (X.values * np.repeat(lab, np.diff(X.col_ptr))).astype(np.float32)
+    cols = CSC(m=d_feat, n=n_ex, col_ptr=X.col_ptr, row_idx=X.row_idx, values=vals)
+    del X, S
+    lam = 1e-3
+    res = {}
+    for tau in (4096, 65536):
+        model = dict(loss="square", scale=1.0 / (lam * n_ex * n_ex), linear=-1.0 / n_ex, lower=0.0, upper=1.0)
+        with pc.Problem(cols, np.zeros(d_feat), 0.0, tau, seed=0, model=model) as p:
+            spe = -(-n_ex // tau)
+            rows = []
+            for epoch in range(1, 6):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                p.step(spe)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                F, _ = p.objective()
+                rows.append({"epoch": epoch, "dual_objective": -F, "seconds": dt,
+                             "updates_per_s": spe * tau / dt})
+            res[str(tau)] = {"beta": p.info()["beta"], "omega": p.info()["omega"], "epochs": rows}
+            print(f"[bench] svm dual tau={tau}: {res[str(tau)]}", file=sys.stderr, flush=True)
+    out["svm_dual"] = {"workload": "svm_dual_677399x47236_d73", "lambda": lam, "tau": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,11 +476,12 @@ def main() -> int:
     ap.add_argument("--gap-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models"],
                     help="single: one instance (default); batched: the uneven lambda path; "
                          "dtypes: time to gap with float64 / float32 / bf16 values; taus: tau sweep "
                          "on both 1e7-column instances; samplings: nice / independent / binomial / "
-                         "masked slots; async: asynchronous variant vs synchronous steps")
+                         "masked slots; async: asynchronous variant vs synchronous steps; models: "
+                         "logistic regression and the SVM dual")
     ap.add_argument("--count", type=int, default=64, help="problems in the batched mode")
     ap.add_argument("--check-steps", type=int, default=64, help="batched mode: steps between gap checks")
     args = ap.parse_args()
@@ -427,6 +504,8 @@ def main() -> int:
         return run_samplings(args)
     if args.mode == "async":
         return run_async(args)
+    if args.mode == "models":
+        return run_models(args)
 
     import numpy as np
     import torch

@@ -200,3 +200,18 @@ def test_nonnegative_lasso_kkt():
     on = s.x > 0
     np.testing.assert_allclose(g[on], -l1, atol=1e-9)
     assert np.all(g[~on] >= -l1 - 1e-9)
+
+
+def test_logistic_objective_at_zero_printed_value():
+    """F(x_0) = 13,352,855 printed for the logistic experiment: with x_0 = 0
+    every one of the 19,264,097 examples contributes log(1 + e^0)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")) as fh:
+        g = json.load(fh)["kddb_logistic_F_x0"]
+    m = g["examples"]
+    A = CSC(m=m, n=1, col_ptr=np.array([0, 1], dtype=np.int64), row_idx=np.array([0], dtype=np.int32),
+            values=np.array([1.0]))
+    y = np.where(np.arange(m) % 2 == 0, 1.0, -1.0)
+    s = oracle.ModelSolver(A, y, tau=1, seed=0, loss="logistic", l2=2.0)
+    assert abs(s.objective() - g["F_x0_printed"]) <= g["printed_abs_tol"]
