@@ -415,13 +415,17 @@ def run_models(args) -> int:
             F0, _ = p.objective()
             rows = []
             for epoch in range(1, 4):
+                p.set_option("kernel_timing", 1)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
                 p.step(spe)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t1
+                kt = {k: p.kernel_time(k)[1] for k in ("gather", "scatter", "refresh")}
+                p.set_option("kernel_timing", 0)
                 F, _ = p.objective()
-                rows.append({"epoch": epoch, "F0_over_F": F0 / F, "seconds": dt, "updates_per_s": spe * tau / dt})
+                rows.append({"epoch": epoch, "F0_over_F": F0 / F, "seconds": dt, "updates_per_s": spe * tau / dt,
+                             "kernel_ms": kt})
             res[str(tau)] = {"beta": p.info()["beta"], "omega": p.info()["omega"], "F0": F0, "epochs": rows}
             print(f"[bench] logistic tau={tau}: {res[str(tau)]}", file=sys.stderr, flush=True)
     out["logistic_l2"] = {"workload": "logistic_19264097x29890095_d19", "nnz": n_feat * d, "tau": res}
@@ -461,6 +465,64 @@ def run_models(args) -> int:
     return 0
 
 
+def run_path(args) -> int:
+    """A 64-point regularisation path on one instance of the batched
+    workload's largest size (n = 1e6 columns, m = 2e5, 10 nonzeros per
+    column): lambda_j = 0.5 * 0.01^(j/63) * ||A^T b||_inf, each solved to a
+    certified 1e-6 gap, (a) warm-started in order, (b) cold from x = 0 one
+    after the other, (c) cold, all 64 as one batch of copies of (A, b)."""
+    import numpy as np
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import planted_lasso, random_csc
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(0)
+    n, m, d = 1_000_000, 200_000, 10
+    A = random_csc(m, n, d, rng, normalize=False, dtype=args.dtype)
+    inst = planted_lasso(A, n // 100, 0.01, 0.5, rng)
+    tau = 4096
+    lam_max = inst.lam / 0.5
+    lams = [0.5 * 0.01 ** (j / 63) * lam_max for j in range(64)]
+    out = {"metric": METRIC, "mode": "path", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": "lasso_path_2e5x1e6_d10", "points": 64, "tau": tau, "target_rel_gap": 1e-6}}
+    with pc.Problem(inst.A, inst.b, lams[0], tau, seed=0) as p:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        path = p.solve_path(lams, rel_gap=1e-6, keep_x=False)
+        torch.cuda.synchronize()
+        out["warm_seconds"] = time.perf_counter() - t0
+        out["warm_epochs"] = sum(st["epochs"] for st in path)
+        out["warm_converged"] = all(st["converged"] for st in path)
+    print(f"[bench] warm path {out['warm_seconds']:.2f}s", file=sys.stderr, flush=True)
+    cold_t = 0.0
+    cold_e = 0
+    with pc.Problem(inst.A, inst.b, lams[0], tau, seed=0) as p:
+        for lam in lams:
+            p.set_option("lambda", lam)
+            p.set_x(np.zeros(n), k=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = p.solve(rel_gap=1e-6, check_every=1)
+            torch.cuda.synchronize()
+            cold_t += time.perf_counter() - t0
+            cold_e += st["epochs"]
+    out["cold_seconds"] = cold_t
+    out["cold_epochs"] = cold_e
+    print(f"[bench] cold path {cold_t:.2f}s", file=sys.stderr, flush=True)
+    with pc.Batch([(inst.A, inst.b, lam, tau) for lam in lams], seed=0) as B:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = B.solve(rel_gap=1e-6, check_every_steps=64)
+        torch.cuda.synchronize()
+        out["batched_cold_seconds"] = time.perf_counter() - t0
+        out["batched_converged"] = st["converged"]
+    out["warm_speedup_vs_cold"] = out["cold_seconds"] / out["warm_seconds"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -476,12 +538,12 @@ def main() -> int:
     ap.add_argument("--gap-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models", "path"],
                     help="single: one instance (default); batched: the uneven lambda path; "
                          "dtypes: time to gap with float64 / float32 / bf16 values; taus: tau sweep "
                          "on both 1e7-column instances; samplings: nice / independent / binomial / "
                          "masked slots; async: asynchronous variant vs synchronous steps; models: "
-                         "logistic regression and the SVM dual")
+                         "logistic regression and the SVM dual; path: warm-started regularisation path")
     ap.add_argument("--count", type=int, default=64, help="problems in the batched mode")
     ap.add_argument("--check-steps", type=int, default=64, help="batched mode: steps between gap checks")
     args = ap.parse_args()
@@ -506,6 +568,8 @@ def main() -> int:
         return run_async(args)
     if args.mode == "models":
         return run_models(args)
+    if args.mode == "path":
+        return run_path(args)
 
     import numpy as np
     import torch

@@ -248,6 +248,27 @@ class Problem:
                 break
         return {"epochs": epochs, "F": F, "gap": gap, "rel_gap": rel, "converged": rel <= rel_gap}
 
+    def solve_path(self, lambdas, rel_gap: float = 1e-6, check_every: int = 1, max_epochs: int = 100000,
+                   keep_x: bool = True) -> list:
+        """Warm-started regularisation path: for each lambda in the given order
+        (largest first is the usual order) set lambda and step on from the
+        previous solution until the certified gap (F - D)/D <= rel_gap (no
+        step when the warm start already meets it).  One dict per lambda:
+        lambda, epochs, F, gap, rel_gap, converged and (keep_x) x."""
+        out = []
+        for lam in lambdas:
+            self.set_option("lambda", float(lam))
+            F, gap = self.objective(gap=True)
+            rel = gap / max(abs(F - gap), 1e-300)
+            st = {"epochs": 0, "F": F, "gap": gap, "rel_gap": rel, "converged": rel <= rel_gap}
+            if not st["converged"]:
+                st = self.solve(rel_gap, check_every, max_epochs)
+            st["lambda"] = float(lam)
+            if keep_x:
+                st["x"] = self.get_x()
+            out.append(st)
+        return out
+
 
 def sample(seed: int, k: int, tau: int, n: int):
     """S_k of the tau-nice sampler as an int32 CUDA tensor (slot order)."""
