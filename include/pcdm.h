@@ -104,6 +104,7 @@ typedef struct pcdm_info {
     double expected_set_size;/* E|S_k| of the sampling (drop mask not included)   */
     int64_t mask_len;        /* slots covered by the drop mask (0 = none)         */
     int64_t narrow_below;    /* tau below which a slot gets a group of lanes      */
+    int64_t nblocks;         /* blocks of a block problem (0: coordinates)        */
     int32_t loss;            /* pcdm_loss of the model (PCDM_LOSS_SQUARE: LASSO)  */
     int32_t reserved1;
     double loss_scale;       /* model terms (see pcdm_model); lambda is l1       */
@@ -177,6 +178,30 @@ typedef struct pcdm_model {
  */
 int pcdm_create_model(const pcdm_csc *A, const double *y, const pcdm_model *model, int64_t tau,
                       uint64_t seed, pcdm_problem **out);
+
+/*
+ * Blocks of several coordinates: the group LASSO
+ *     F(x) = 0.5||A x - b||^2 + lambda sum_i ||x^(i)||_2
+ * (section "Block structure, notation and assumptions"; the group-lasso
+ * example of a block separable Omega).  Block i is the column range
+ * block_ptr[i] .. block_ptr[i+1]-1 (block_ptr [nblocks+1] int64, 0 = first,
+ * n = last, 1 to 16 columns per block; host or device as A->on_device says;
+ * order the columns so that each group is consecutive).  Euclidean block
+ * norms, so L_i = lambda_max(A_i^T A_i) (computed at create from the block's
+ * Gram matrix by Jacobi rotations in float64); omega = the largest number of
+ * distinct blocks with a nonzero in one row; tau counts blocks (1 <= tau <=
+ * nblocks) with the tau-nice sampler over blocks and beta = 1 + (omega-1)
+ * (tau-1)/max(1, nblocks-1).  The update of a sampled block is the block
+ * soft threshold max(0, 1 - lambda/(beta L_i ||u||)) u with u = x^(i) -
+ * A_i^T r/(beta L_i).  pcdm_step, pcdm_objective (with the duality gap for
+ * theta = r min(1, lambda / max_i ||A_i^T r||)), pcdm_get_x / set_x,
+ * pcdm_set_rhs, the lambda / tau / refresh_every / lanes_per_column options
+ * and pcdm_autotune serve block problems; other samplings, slot masks, the
+ * adjoint and the asynchronous variant do not (PCDM_EINVAL).  Extra device
+ * memory: 8 (nblocks + 1) + 8 nblocks + n * sizeof(working type) bytes.
+ */
+int pcdm_create_group(const pcdm_csc *A, const double *b, double lambda, const int64_t *block_ptr,
+                      int64_t nblocks, int64_t tau, uint64_t seed, pcdm_problem **out);
 
 /* Free all device memory of the handle (synchronises the device). NULL is a no-op. */
 int pcdm_destroy(pcdm_problem *h);

@@ -19,6 +19,7 @@ EXPORTS = ("pcdm_create", "pcdm_destroy", "pcdm_last_error", "pcdm_set_option", 
            "pcdm_step", "pcdm_objective", "pcdm_get_x", "pcdm_set_x", "pcdm_get_residual",
            "pcdm_grad_backward", "pcdm_set_rhs", "pcdm_kernel_time", "pcdm_autotune", "pcdm_sample",
            "pcdm_sample_draw", "pcdm_set_slot_mask", "pcdm_step_async", "pcdm_create_model",
+           "pcdm_create_group",
            "pcdm_batch_create", "pcdm_batch_step", "pcdm_batch_objective", "pcdm_batch_set_active",
            "pcdm_batch_get_x", "pcdm_batch_get_info", "pcdm_batch_set_option", "pcdm_batch_autotune",
            "pcdm_batch_destroy")
@@ -39,7 +40,8 @@ class pcdm_info(ctypes.Structure):
                 ("lanes_per_column", ctypes.c_int32), ("chunks_per_lane", ctypes.c_int32),
                 ("sampling", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("binomial_p", ctypes.c_double),
                 ("expected_set_size", ctypes.c_double), ("mask_len", ctypes.c_int64),
-                ("narrow_below", ctypes.c_int64), ("loss", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("narrow_below", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("loss", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32),
                 ("loss_scale", ctypes.c_double), ("l2", ctypes.c_double), ("linear", ctypes.c_double),
                 ("lower", ctypes.c_double), ("upper", ctypes.c_double), ("async_picks", ctypes.c_int64),
                 ("async_processors", ctypes.c_int64)]
@@ -78,6 +80,7 @@ def load() -> ctypes.CDLL:
             "pcdm_destroy": [vp],
             "pcdm_create_model": [ctypes.POINTER(pcdm_csc), vp, ctypes.POINTER(pcdm_model), i64, u64,
                                   ctypes.POINTER(vp)],
+            "pcdm_create_group": [ctypes.POINTER(pcdm_csc), vp, f64, vp, i64, i64, u64, ctypes.POINTER(vp)],
             "pcdm_set_option": [vp, ctypes.c_char_p, f64],
             "pcdm_get_info": [vp, ctypes.POINTER(pcdm_info)],
             "pcdm_step": [vp, i64, vp],

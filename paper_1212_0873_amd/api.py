@@ -49,11 +49,14 @@ class Problem:
     ``b`` is float64 in the same place.
     """
 
-    def __init__(self, A, b, lam: float, tau: int, seed: int = 0, model: Optional[dict] = None):
+    def __init__(self, A, b, lam: float, tau: int, seed: int = 0, model: Optional[dict] = None,
+                 blocks=None):
         """``model`` (optional) selects another loss / regulariser
         (``pcdm_create_model``): keys loss ('square', 'logistic', 'sqhinge'),
         scale, l2, linear, lower, upper; ``lam`` is the l1 weight and ``b``
-        the targets or +-1 labels."""
+        the targets or +-1 labels.  ``blocks`` (optional, int64 [nblocks+1]
+        column boundaries) makes a group LASSO (``pcdm_create_group``) whose
+        tau counts blocks."""
         self._lib = load()
         self._h = ctypes.c_void_p()
         on_dev = not isinstance(A.values, np.ndarray)
@@ -77,7 +80,18 @@ class Problem:
         desc = pcdm_csc(int(A.m), int(A.n), nnz, _ptr(cp), _ptr(ri), _ptr(vals), dtype, int(on_dev))
         if on_dev:
             _torch().cuda.current_stream().synchronize()
-        if model is None:
+        if blocks is not None:
+            if model is not None:
+                raise ValueError("a block problem is a group LASSO: no model")
+            if on_dev:
+                bpk = blocks.to(_torch().int64).contiguous()
+                nblk = int(bpk.numel()) - 1
+            else:
+                bpk = np.ascontiguousarray(blocks, dtype=np.int64)
+                nblk = int(bpk.size) - 1
+            check(self._lib.pcdm_create_group(ctypes.byref(desc), _ptr(bb), float(lam), _ptr(bpk), nblk, int(tau),
+                                              int(seed) & (2**64 - 1), ctypes.byref(self._h)))
+        elif model is None:
             check(self._lib.pcdm_create(ctypes.byref(desc), _ptr(bb), float(lam), int(tau),
                                         int(seed) & (2**64 - 1), ctypes.byref(self._h)))
         else:
@@ -234,7 +248,8 @@ class Problem:
     def solve(self, rel_gap: float = 1e-6, check_every: int = 5, max_epochs: int = 100000) -> dict:
         """Step until the certified duality gap (F - D)/D <= rel_gap; returns
         {"epochs", "F", "gap", "rel_gap", "converged"}."""
-        spe = -(-self.n // self.info()["tau"])
+        inf = self.info()
+        spe = -(-(inf["nblocks"] or self.n) // inf["tau"])  # one epoch: every coordinate or block once
         epochs = 0
         F = gap = None
         rel = float("inf")

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "group_kernels.hpp"
 #include "kernels.hpp"
 #include "pcdm.h"
 
@@ -130,6 +131,13 @@ struct pcdm_problem {
     int loss = kLossSquare;
     double lscale = 1.0, l2 = 0.0, lin = 0.0, lo = -HUGE_VAL, hi = HUGE_VAL;
 
+    // blocks of several coordinates (group LASSO): block i = columns bp[i] .. bp[i+1]-1
+    int group = 0;
+    int64_t nb = 0;
+    int64_t *bp = nullptr;    // [nb+1] device
+    double *invlb = nullptr;  // [nb] 1 / lambda_max(A_i^T A_i)
+    void *dx = nullptr;       // [n] per-column change of the last step (working type)
+
     // asynchronous variant
     int cus = 0;
     int async_reads = -1;      // kReadCached / kReadAcquire / kReadAtomic, -1 = by processor count
@@ -163,7 +171,7 @@ void free_problem(pcdm_problem *P)
     for (hipEvent_t e : P->event_pool)
         (void)hipEventDestroy(e);
     void *bufs[] = {P->seg, P->pc, P->x, P->r, P->r64, P->b64, P->id_slot,
-                    P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim};
+                    P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim, P->bp, P->invlb, P->dx};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -216,7 +224,7 @@ double expected_set_size(const pcdm_problem *P)
 // tau-independent picks; binomial row).  beta_rule 1: min(omega, tau).
 int compute_beta(pcdm_problem *P)
 {
-    const double om = (double)P->omega, ta = (double)P->tau, nn = (double)P->n;
+    const double om = (double)P->omega, ta = (double)P->tau, nn = (double)(P->group ? P->nb : P->n);
     const double den = std::max(1.0, nn - 1.0);
     if (P->beta_rule == 0) {
         if (P->sampling == kSampleIndependent) {
@@ -252,7 +260,7 @@ SlotPlan slot_plan(const pcdm_problem *P)
 // variant) require it.
 bool is_lasso(const pcdm_problem *P)
 {
-    return P->loss == kLossSquare && P->lscale == 1.0 && P->l2 == 0.0 && P->lin == 0.0 && P->lo == -HUGE_VAL &&
+    return !P->group && P->loss == kLossSquare && P->lscale == 1.0 && P->l2 == 0.0 && P->lin == 0.0 && P->lo == -HUGE_VAL &&
            P->hi == HUGE_VAL;
 }
 
@@ -488,8 +496,62 @@ template <typename V> struct Ops {
         return PCDM_OK;
     }
 
+    template <int G> static void launch_group(pcdm_problem *P, hipStream_t s)
+    {
+        const int grid = grid_for(P->tau * G, kBlock, P->nblk_max);
+        hipEvent_t t0 = clock_start(P, s);
+        hipLaunchKernelGGL((k_group_gather<V, G>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay, (const T *)P->r,
+                           P->x, (const int64_t *)P->bp, (const double *)P->invlb, P->id_slot, (T *)P->dx, P->ctrl,
+                           P->nz_part, P->seed, P->tau, (uint32_t)P->nb, 1.0 / P->beta, P->lambda);
+        clock_stop(P, CLK_GATHER, t0, s);
+        hipEvent_t t1 = clock_start(P, s);
+        hipLaunchKernelGGL((k_group_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                           (T *)P->r, (const int64_t *)P->bp, (const int32_t *)P->id_slot, (const T *)P->dx, P->ctrl,
+                           P->tau);
+        clock_stop(P, CLK_SCATTER, t1, s);
+    }
+
+    static int group_once(pcdm_problem *P, hipStream_t s)
+    {
+        switch (P->lanes) {
+        case 1: launch_group<1>(P, s); return PCDM_OK;
+        case 2: launch_group<2>(P, s); return PCDM_OK;
+        case 4: launch_group<4>(P, s); return PCDM_OK;
+        case 8: launch_group<8>(P, s); return PCDM_OK;
+        case 16: launch_group<16>(P, s); return PCDM_OK;
+        case 32: launch_group<32>(P, s); return PCDM_OK;
+        case 64: launch_group<64>(P, s); return PCDM_OK;
+        default: return fail(PCDM_EINVAL, "unsupported lanes_per_column");
+        }
+    }
+
+    // ctrl->scal[2] = sum_i ||x^(i)||, and with gap ctrl->scal[3] = max_i ||A_i^T r64||.
+    static void group_sums(pcdm_problem *P, bool gap, hipStream_t s)
+    {
+        const int g = grid_for(P->nb, kBlock, P->nblk_max);
+        hipLaunchKernelGGL(k_group_xnorms, dim3(g), dim3(kBlock), 0, s, (const int64_t *)P->bp, P->nb,
+                           (const double *)P->x, P->part2);
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, g, 1, 0, P->ctrl->scal + 2);
+        if (gap) {
+            const int ga = grid_for(P->nb * 8, kBlock, P->nblk_max);
+            hipLaunchKernelGGL((k_group_atr<V, 8>), dim3(ga), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                               (const double *)P->r64, (const int64_t *)P->bp, P->nb, P->part2);
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, ga, 1, 1,
+                               P->ctrl->scal + 3);
+        }
+    }
+
+    static void group_setup(pcdm_problem *P, int32_t *hist, hipStream_t s)
+    {
+        const int g = grid_for(P->nb, 1, 4 * P->nblk_max);
+        hipLaunchKernelGGL((k_group_setup<V>), dim3(g), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                           (const int64_t *)P->bp, P->nb, P->invlb, hist, P->ctrl);
+    }
+
     static int step_once(pcdm_problem *P, hipStream_t s)
     {
+        if (P->group)
+            return group_once(P, s);
         switch (P->loss) {
         case kLossLogistic: return step_loss<kLossLogistic>(P, s);
         case kLossSqHinge: return step_loss<kLossSqHinge>(P, s);
@@ -951,6 +1013,83 @@ int pcdm_create_model(const pcdm_csc *A, const double *y, const pcdm_model *mode
     }
 }
 
+int pcdm_create_group(const pcdm_csc *A, const double *b, double lambda, const int64_t *block_ptr, int64_t nblocks,
+                      int64_t tau, uint64_t seed, pcdm_problem **out)
+{
+    t_err.clear();
+    if (out)
+        *out = nullptr;
+    if (!A || !block_ptr || !out)
+        return fail(PCDM_EINVAL, "NULL argument");
+    if (nblocks < 1 || nblocks > A->n)
+        return fail(PCDM_EINVAL, "need 1 <= nblocks <= n");
+    if (tau < 1 || tau > nblocks)
+        return fail(PCDM_EINVAL, "need 1 <= tau <= nblocks");
+    std::vector<int64_t> hbp((size_t)nblocks + 1);
+    if (A->on_device) {
+        HIP_TRY(hipMemcpy(hbp.data(), block_ptr, hbp.size() * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(hbp.data(), block_ptr, hbp.size() * 8);
+    }
+    if (hbp[0] != 0 || hbp[(size_t)nblocks] != A->n)
+        return fail(PCDM_EINVAL, "block_ptr must start at 0 and end at n");
+    for (int64_t i = 0; i < nblocks; ++i) {
+        const int64_t sz = hbp[(size_t)i + 1] - hbp[(size_t)i];
+        if (sz < 1 || sz > kGroupMax)
+            return fail(PCDM_EINVAL, "every block needs 1 to 16 columns (block_ptr strictly increasing)");
+    }
+    pcdm_problem *P = nullptr;
+    try {
+        PCDM_TRY(create_impl(A, b, lambda, 1, seed, nullptr, &P));
+    } catch (...) {
+        return fail(PCDM_EDEVICE, "exception during create");
+    }
+    struct Guard {
+        pcdm_problem *p;
+        ~Guard() { free_problem(p); }
+    } guard{P};
+    hipStream_t s = nullptr;
+    P->group = 1;
+    P->nb = nblocks;
+    HIP_TRY(hipMalloc(&P->bp, hbp.size() * 8));
+    HIP_TRY(hipMemcpy(P->bp, hbp.data(), hbp.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&P->invlb, (size_t)nblocks * 8));
+    HIP_TRY(hipMalloc(&P->dx, (size_t)P->n * P->tbytes));
+    int32_t *hist = nullptr;
+    HIP_TRY(hipMalloc(&hist, (size_t)P->m * 4));
+    hipError_t e = hipMemset(hist, 0, (size_t)P->m * 4);
+    if (e == hipSuccess) {
+        (void)dispatch(P->dtype, [&](auto ops) {
+            decltype(ops)::group_setup(P, hist, s);
+            return PCDM_OK;
+        });
+        const int g = grid_for(P->m, kBlock, P->nblk_max);
+        hipLaunchKernelGGL(k_imax_partials, dim3(g), dim3(kBlock), 0, s, (const int32_t *)hist, P->m,
+                           (int64_t *)P->part2);
+        hipLaunchKernelGGL(k_imax_final, dim3(1), dim3(kBlock), 0, s, (const int64_t *)P->part2, g, P->ctrl);
+        e = hipDeviceSynchronize();
+    }
+    (void)hipFree(hist);
+    if (e != hipSuccess)
+        return hip_fail(e, "group set-up");
+    PCDM_TRY(check_launch("group set-up"));
+    Ctrl hc;
+    HIP_TRY(hipMemcpy(&hc, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (hc.err)
+        return fail(PCDM_EINVAL, "invalid block: " + describe_err(hc.err));
+    P->omega = hc.imax;
+    PCDM_TRY(ensure_slots(P, tau));
+    P->tau = tau;
+    P->lanes = 8;
+    P->chunks = 1;
+    P->lanes_auto = 1;
+    compute_beta(P);
+    P->refresh_every = ceil_div(P->nb, P->tau);
+    guard.p = nullptr;
+    *out = P;
+    return PCDM_OK;
+}
+
 int pcdm_destroy(pcdm_problem *h)
 {
     if (!h)
@@ -989,8 +1128,9 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         h->lambda = value;
     } else if (k == "tau") {
         const int64_t t = (int64_t)value;
-        if ((double)t != value || t < 1 || t > h->n)
-            return fail(PCDM_EINVAL, "tau must be an integer in [1, n]");
+        const int64_t units = h->group ? h->nb : h->n;
+        if ((double)t != value || t < 1 || t > units)
+            return fail(PCDM_EINVAL, "tau must be an integer in [1, n] (n blocks for a block problem)");
         PCDM_TRY(ensure_slots(h, t));
         h->tau = t;
         compute_beta(h);
@@ -1004,7 +1144,7 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         } else {
             const int g = k == "lanes_per_column" ? v : h->lanes;
             const int c = k == "chunks_per_lane" ? v : (schedule_supported(v, h->chunks, h->loss) ? h->chunks : 1);
-            if (!schedule_supported(g, c, h->loss))
+            if (!schedule_supported(g, c, h->loss) || (h->group && c != 1))
                 return fail(PCDM_EINVAL, "unsupported (lanes_per_column, chunks_per_lane) pair");
             h->lanes = g;
             h->chunks = c;
@@ -1012,6 +1152,8 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         }
     } else if (k == "sampling") {
         const int v = (int)value;
+        if (h->group && value != 0.0)
+            return fail(PCDM_EINVAL, "block problems use the tau-nice sampling");
         if ((double)v != value || v < kSampleNice || v > kSampleBinomial)
             return fail(PCDM_EINVAL, "sampling must be 0 (tau-nice), 1 (tau-independent) or 2 (binomial)");
         if (v == kSampleIndependent && !h->claim) {
@@ -1107,6 +1249,7 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->expected_set_size = expected_set_size(h);
     out->mask_len = h->mask_len;
     out->narrow_below = h->narrow_below;
+    out->nblocks = h->group ? h->nb : 0;
     out->loss = h->loss;
     out->loss_scale = h->lscale;
     out->l2 = h->l2;
@@ -1166,6 +1309,26 @@ int pcdm_objective(pcdm_problem *h, double *F, double *dual_gap, void *stream)
         return fail(PCDM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     h->last_stream = s;
+    if (h->group) {
+        PCDM_TRY(dispatch(h->dtype, [&](auto ops) {
+            decltype(ops)::residual64(h, s);
+            decltype(ops)::sums(h, s);
+            decltype(ops)::group_sums(h, dual_gap != nullptr, s);
+            return PCDM_OK;
+        }));
+        PCDM_TRY(check_launch("pcdm_objective"));
+        double sc[4] = {0, 0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(sc, h->ctrl->scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const double rr = sc[0], br = sc[1], gn = sc[2];
+        *F = 0.5 * rr + h->lambda * gn;
+        if (dual_gap) {
+            const double gmax = sc[3];
+            const double th = (gmax > h->lambda) ? h->lambda / gmax : 1.0;
+            *dual_gap = *F - (-0.5 * th * th * rr - th * br);
+        }
+        return PCDM_OK;
+    }
     if (!is_lasso(h)) {
         if (dual_gap)
             return fail(PCDM_EINVAL, "the duality gap is computed for the LASSO only (square loss, l1 term)");
@@ -1493,7 +1656,7 @@ int pcdm_autotune(pcdm_problem *h, int64_t steps_per_candidate, void *stream)
     const int64_t widths[2] = {0, INT64_MAX};
     for (int64_t nb : widths) {
         for (const auto &c : cand) {
-            if (!schedule_supported(c[0], c[1], h->loss))
+            if (!schedule_supported(c[0], c[1], h->loss) || (h->group && c[1] != 1))
                 continue;
             h->lanes = c[0];
             h->chunks = c[1];
@@ -1555,6 +1718,8 @@ int pcdm_set_slot_mask(pcdm_problem *h, const uint8_t *mask, int64_t len, int32_
 {
     if (!h)
         return fail(PCDM_EINVAL, "NULL handle");
+    if (h->group)
+        return fail(PCDM_EINVAL, "block problems take no slot mask");
     if (len < 0 || (len > 0 && !mask))
         return fail(PCDM_EINVAL, "need len >= 0 and a mask when len > 0");
     if (len > h->n)
