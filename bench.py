@@ -523,6 +523,58 @@ def run_path(args) -> int:
     return 0
 
 
+def run_group(args) -> int:
+    """Group LASSO on the 1e6 x 1e7 instance with blocks of 4 consecutive
+    columns (2.5e6 blocks): set-up time (block Gram matrices and their largest
+    eigenvalues), coordinate updates/s and time to a certified 1e-6 gap at
+    tau = 2.5e5 blocks (1e6 coordinates per step), lambda = 0.05 max_i
+    ||A_i^T b||."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import make_config
+
+    torch.cuda.set_device(0)
+    inst = make_config("lasso_1e6x1e7", dtype=args.dtype)
+    A = inst.A
+    size = 4
+    bp = np.arange(0, A.n + 1, size, dtype=np.int64)
+    S = sp.csc_matrix((A.values_f64(), A.row_idx, A.col_ptr), shape=(A.m, A.n))
+    atb = S.T @ inst.b
+    lam = 0.05 * float(np.max(np.sqrt(np.add.reduceat(atb * atb, bp[:-1]))))
+    del S, atb
+    tau = 250_000
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = pc.Problem(A, inst.b, lam, tau, seed=0, blocks=bp)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    inf = p.info()
+    spe = -(-inf["nblocks"] // tau)
+    p.step(10)
+    p.set_option("kernel_timing", 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.step(200)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ng, gms = p.kernel_time("gather")
+    ns, sms = p.kernel_time("scatter")
+    p.set_option("kernel_timing", 0)
+    p.set_x(np.zeros(A.n), k=0)
+    ttg = time_to_gap(p, spe, 1e-6, args.gap_seconds)
+    p.close()
+    out = {"metric": METRIC, "mode": "group", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": "group_lasso_1e6x1e7_d20_blocks4", "nblocks": inf["nblocks"], "tau_blocks": tau,
+                      "omega_blocks": inf["omega"], "beta": inf["beta"], "lambda": lam},
+           "create_seconds": create_s, "coord_updates_per_s": 200 * tau * size / dt, "ms_per_step": dt / 200 * 1e3,
+           "gather_avg_us": gms / max(ng, 1) * 1e3, "scatter_avg_us": sms / max(ns, 1) * 1e3, "time_to_gap": ttg}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -538,12 +590,13 @@ def main() -> int:
     ap.add_argument("--gap-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models", "path"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models", "path", "group"],
                     help="single: one instance (default); batched: the uneven lambda path; "
                          "dtypes: time to gap with float64 / float32 / bf16 values; taus: tau sweep "
                          "on both 1e7-column instances; samplings: nice / independent / binomial / "
                          "masked slots; async: asynchronous variant vs synchronous steps; models: "
-                         "logistic regression and the SVM dual; path: warm-started regularisation path")
+                         "logistic regression and the SVM dual; path: warm-started regularisation path; "
+                         "group: group LASSO with blocks of 4 columns")
     ap.add_argument("--count", type=int, default=64, help="problems in the batched mode")
     ap.add_argument("--check-steps", type=int, default=64, help="batched mode: steps between gap checks")
     args = ap.parse_args()
@@ -570,6 +623,8 @@ def main() -> int:
         return run_models(args)
     if args.mode == "path":
         return run_path(args)
+    if args.mode == "group":
+        return run_group(args)
 
     import numpy as np
     import torch

@@ -145,7 +145,8 @@ k_group_setup(const char *__restrict__ seg, Layout lay, const int64_t *__restric
 // Phase 1 of a group step: a group of G lanes per sampled block (64/G blocks
 // per wave).  Every lane of the group reads the block's columns with the
 // same column dot as the coordinate path; the new block, x and dx (the
-// change per column, read by the scatter) are written by the group's lanes.
+// change per column, read by the scatter) are written by the group's lanes;
+// the slot holds the block, or its complement when nothing changed.
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
 k_group_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
@@ -216,7 +217,7 @@ k_group_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__
             }
         }
         if (act && gl == 0) {
-            id_slot[slot] = (int32_t)i;
+            id_slot[slot] = changed ? (int32_t)i : ~(int32_t)i;  // ~i: nothing to scatter
             if (changed)
                 ++nz;
         }
@@ -226,8 +227,8 @@ k_group_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__
         nz_part[blockIdx.x] += tot;
 }
 
-// Phase 2: r += A_i dx^(i) for the sampled blocks (columns with dx != 0),
-// hardware float atomics; advances the step counter.
+// Phase 2: r += A_i dx^(i) for the sampled blocks that changed (slot id >= 0;
+// columns with dx != 0), hardware float atomics; advances the step counter.
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
 k_group_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restrict__ r,
@@ -245,6 +246,8 @@ k_group_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *_
         if (slot >= tau)
             continue;
         const int32_t i = id_slot[slot];
+        if (i < 0)
+            continue;  // block unchanged this step
         const int64_t c0 = bp[i];
         const int N = (int)(bp[i + 1] - c0);
         for (int c = 0; c < N; ++c) {
