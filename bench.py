@@ -636,6 +636,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     dev_name = torch.cuda.get_device_name(0)
 
+    copy_gbps = copy_bandwidth_gbps()
     if args.copy_calibration:
         nb = 1 << 30
         src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -729,7 +730,11 @@ def main() -> int:
                      "traffic": traffic, "alg_bytes_per_update": b_gather,
                      "launches": ng, "avg_launch_us": gather_avg_s * 1e6,
                      "measured_gbps": (traffic / gather_avg_s / 1e9) if traffic else None,
-                     "measured_frac": (traffic / gather_avg_s / 1e9 / HBM_PEAK_GBPS) if traffic else None},
+                     "measured_frac": (traffic / gather_avg_s / 1e9 / HBM_PEAK_GBPS) if traffic else None,
+                     "measured_over_algorithmic": (traffic / gather_bytes) if traffic else None,
+                     "copy_gbps": copy_gbps,
+                     "frac_of_copy": achieved / copy_gbps,
+                     "measured_frac_of_copy": (traffic / gather_avg_s / 1e9 / copy_gbps) if traffic else None},
         "hbm_gbps_algorithmic_step": step_alg_bytes / t_el / 1e9,
         "nonzero_update_fraction": nz / updates,
         "kernel_ms": {"gather": gms, "scatter": sms, "refresh": rms,
