@@ -251,6 +251,12 @@ const char *pcdm_last_error(void);
  *   "async_processors" processors of pcdm_step_async: 0 (default) = min(tau,
  *                      lane groups the device holds at once), else that count;
  *   "async_reads", "async_rounds": see pcdm_step_async;
+ *   "graph_steps"      runs of this many steps (default 32; 0 = off) are
+ *                      captured once into a HIP graph (on an internal stream)
+ *                      and replayed on the caller's stream, when no float64
+ *                      refresh falls inside the run and "kernel_timing" is
+ *                      off; the graph is rebuilt whenever an argument of the
+ *                      step kernels changes (options, masks, sampling);
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
  *                      settings of pcdm_grad_backward's solve (see there);

@@ -138,6 +138,14 @@ struct pcdm_problem {
     double *invlb = nullptr;  // [nb] 1 / lambda_max(A_i^T A_i)
     void *dx = nullptr;       // [n] per-column change of the last step (working type)
 
+    // runs of steps captured into a graph and replayed
+    int64_t graph_len = 32;  // steps per graph; 0 = launch every step directly
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_sig;  // step-kernel arguments the graph was captured with
+    int64_t graph_captured_len = 0;
+
     // asynchronous variant
     int cus = 0;
     int async_reads = -1;      // kReadCached / kReadAcquire / kReadAtomic, -1 = by processor count
@@ -159,10 +167,24 @@ struct pcdm_problem {
 
 namespace {
 
+void drop_step_graph(pcdm_problem *P)
+{
+    if (P->graph_exec)
+        (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->graph)
+        (void)hipGraphDestroy(P->graph);
+    P->graph_exec = nullptr;
+    P->graph = nullptr;
+    P->graph_sig.clear();
+}
+
 void free_problem(pcdm_problem *P)
 {
     if (!P)
         return;
+    drop_step_graph(P);
+    if (P->cap_stream)
+        (void)hipStreamDestroy(P->cap_stream);
     for (auto &c : P->clocks)
         for (auto &pr : c.pending) {
             (void)hipEventDestroy(pr.first);
@@ -967,6 +989,68 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
     return PCDM_OK;
 }
 
+// Everything the step kernels take from the host, as bytes: a captured graph
+// is valid only while this is unchanged (the step counter is read on the
+// device, so replays advance through successive steps).
+std::vector<unsigned char> step_signature(const pcdm_problem *P)
+{
+    std::vector<unsigned char> sig;
+    auto put = [&](const auto &v) {
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(&v);
+        sig.insert(sig.end(), b, b + sizeof(v));
+    };
+    put(P->tau);
+    put(P->beta);
+    put(P->lambda);
+    put(P->lanes);
+    put(P->chunks);
+    put(P->narrow_below);
+    put(P->loss);
+    put(P->lscale);
+    put(P->l2);
+    put(P->lin);
+    put(P->lo);
+    put(P->hi);
+    put(P->sampling);
+    put(P->pb);
+    put(P->mask);
+    put(P->mask_len);
+    put(P->claim);
+    put(P->claim_base);
+    put(P->group);
+    put(P->seed);
+    put(P->id_slot);
+    put(P->delta_slot);
+    put(P->dx);
+    return sig;
+}
+
+int ensure_step_graph(pcdm_problem *P)
+{
+    std::vector<unsigned char> sig = step_signature(P);
+    if (P->graph_exec && P->graph_captured_len == P->graph_len && sig == P->graph_sig)
+        return PCDM_OK;
+    drop_step_graph(P);
+    if (!P->cap_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    int st = PCDM_OK;
+    for (int64_t q = 0; q < P->graph_len && st == PCDM_OK; ++q)
+        st = dispatch(P->dtype, [&](auto ops) { return decltype(ops)::step_once(P, P->cap_stream); });
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+    if (st != PCDM_OK || e != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st != PCDM_OK ? st : hip_fail(e, "hipStreamEndCapture");
+    }
+    P->graph = g;
+    HIP_TRY(hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0));
+    P->graph_sig = std::move(sig);
+    P->graph_captured_len = P->graph_len;
+    return PCDM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1180,6 +1264,10 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         if (!(value >= 0.0) || value > 9.0e15 || value != std::floor(value))
             return fail(PCDM_EINVAL, "async_rounds must be a non-negative integer");
         h->async_rounds = (int64_t)value;
+    } else if (k == "graph_steps") {
+        if (!(value >= 0.0) || value > 4096.0 || value != std::floor(value))
+            return fail(PCDM_EINVAL, "graph_steps must be an integer in [0, 4096]");
+        h->graph_len = (int64_t)value;
     } else if (k == "narrow_below") {
         if (!(value >= 0.0))
             return fail(PCDM_EINVAL, "narrow_below must be >= 0");
@@ -1269,11 +1357,24 @@ int pcdm_step(pcdm_problem *h, int64_t nsteps, void *stream)
         return fail(PCDM_EINVAL, "nsteps must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     h->last_stream = s;
-    for (int64_t q = 0; q < nsteps; ++q) {
-        if (h->claim && h->k_host - h->claim_base >= (int64_t)0xFFFFFFFE)
+    const int64_t L = h->graph_len;
+    const bool graphs = L > 0 && !h->timing;  // per-launch events need direct launches
+    int64_t left = nsteps;
+    while (left > 0) {
+        if (h->claim && h->k_host - h->claim_base >= (int64_t)0xFFFFFFFE - std::max<int64_t>(L, 1))
             reset_claims(h, h->k_host, s);  // 32-bit stamps must not repeat
-        PCDM_TRY(dispatch(h->dtype, [&](auto ops) { return decltype(ops)::step_once(h, s); }));
-        h->k_host += 1;
+        const int64_t to_refresh =
+            h->refresh_every > 0 ? h->refresh_every - h->k_host % h->refresh_every : INT64_MAX;
+        if (graphs && left >= L && to_refresh >= L) {
+            PCDM_TRY(ensure_step_graph(h));
+            HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+            h->k_host += L;
+            left -= L;
+        } else {
+            PCDM_TRY(dispatch(h->dtype, [&](auto ops) { return decltype(ops)::step_once(h, s); }));
+            h->k_host += 1;
+            left -= 1;
+        }
         if (h->refresh_every > 0 && h->k_host % h->refresh_every == 0)
             PCDM_TRY(refresh_now(h, s));
     }

@@ -400,3 +400,64 @@ def test_narrow_layout_large_tau(pc, dtype):
             ref.step(6)
             F, _ = p.objective()
             assert F == pytest.approx(ref.objective(), rel=1e-5)
+
+
+# --------------------------------------------------------------------------- #
+# runs of steps replayed from a captured graph
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("graph_steps", [0, 5, 32])
+def test_graph_replays_match_oracle(pc, graph_steps):
+    """Calls of odd lengths with a refresh every 25 steps, so runs are split
+    between graph replays and direct launches."""
+    inst = make_config("small_2000x1000", dtype="f64")
+    ref = oracle.Solver(inst.A, inst.b, inst.lam, tau=8, seed=0)
+    with pc.Problem(inst.A, inst.b, inst.lam, 8, seed=0) as p:
+        p.set_option("graph_steps", graph_steps)
+        p.set_option("refresh_every", 25)
+        for n in (37, 64, 5, 101, 32, 77):
+            p.step(n)
+            ref.step(n)
+            F, _ = p.objective()
+            assert F == pytest.approx(ref.objective(), rel=1e-10)
+        np.testing.assert_allclose(p.get_x(), ref.x, rtol=0, atol=1e-9)
+        assert p.info()["k"] == 316
+
+
+def test_graph_rebuilt_when_options_change(pc):
+    """lambda, tau and the sampling change between calls; each change must
+    reach the replayed steps."""
+    inst = make_config("small_2000x1000", dtype="f64")
+    ref = oracle.Solver(inst.A, inst.b, inst.lam, tau=8, seed=4)
+    with pc.Problem(inst.A, inst.b, inst.lam, 8, seed=4) as p:
+        p.set_option("refresh_every", 0)
+        p.step(64)
+        ref.step(64)
+        p.set_option("lambda", inst.lam * 0.5)
+        ref.lam = inst.lam * 0.5
+        p.step(64)
+        ref.step(64)
+        np.testing.assert_allclose(p.get_x(), ref.x, rtol=0, atol=1e-9)
+        p.set_option("tau", 20)
+        ref2 = oracle.Solver(inst.A, inst.b, inst.lam * 0.5, tau=20, seed=4, x0=ref.x)
+        ref2.k = ref.k
+        p.step(64)
+        ref2.step(64)
+        np.testing.assert_allclose(p.get_x(), ref2.x, rtol=0, atol=1e-9)
+        p.set_sampling("independent")
+        ref3 = oracle.Solver(inst.A, inst.b, inst.lam * 0.5, tau=20, seed=4, x0=ref2.x, sampling="independent")
+        ref3.k = ref2.k
+        p.step(96)
+        ref3.step(96)
+        np.testing.assert_allclose(p.get_x(), ref3.x, rtol=0, atol=1e-9)
+
+
+def test_graph_replays_with_independent_picks_rewind(pc):
+    inst = make_config("small_2000x1000", dtype="f64")
+    with pc.Problem(inst.A, inst.b, inst.lam, 300, seed=3) as p:
+        p.set_sampling("independent")
+        p.step(100)
+        x1 = p.get_x()
+        p.set_x(np.zeros(inst.A.n), k=0)
+        p.step(100)
+        np.testing.assert_allclose(p.get_x(), x1, rtol=0, atol=1e-12)
