@@ -758,8 +758,14 @@ def main() -> int:
             ref.step(1)
             steps += 1
         tc = time.perf_counter() - t_c
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": steps * tau / tc, "unit": "coord updates/s", "cores": 1,
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu_model": cpu_model, "host_threads_available": os.cpu_count(),
                                "sample": f"{steps} steps of tau={tau} from x=0 on the same matrix "
                                          f"({steps * tau} updates, {tc:.1f} s, float64, one thread)"}
     print(json.dumps(out), flush=True)
