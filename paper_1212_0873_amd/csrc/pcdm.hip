@@ -71,6 +71,12 @@ int grid_for(int64_t items, int64_t per_block, int cap)
 }
 
 constexpr int kReduceBlocks = 1024;
+
+// Upper bound on the workgroups of a step launch per compute unit (the
+// kernels loop over their tiles, so a smaller grid only changes balance).
+#ifndef PCDM_BLOCKS_PER_CU
+#define PCDM_BLOCKS_PER_CU 8
+#endif
 constexpr int64_t kAsyncAcquireProcs = 8192;  // automatic read mode: acquire up to this many processors
 
 // Device time of one kernel kind, from HIP events recorded around each launch.
@@ -833,7 +839,7 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
     HIP_TRY(hipGetDevice(&P->device));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device));
-    P->nblk_max = std::max(64, cus * 8);
+    P->nblk_max = std::max(64, cus * PCDM_BLOCKS_PER_CU);
     P->cus = cus;
     P->m = A->m;
     P->n = A->n;
