@@ -482,18 +482,58 @@ k_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restri
 
 // Phase 2 of step k: r += delta_i a_i over the slots with delta_i != 0, with
 // hardware float atomics (at most min(omega, tau) columns of one step share
-// a row).  Also advances the step counter for step k+1.
+// a row).  Also advances the step counter for step k+1.  Late in a run few
+// updates are nonzero, scattered over the slots; so each workgroup first
+// packs the nonzero (i, delta_i) of kScatterSpan consecutive slots into LDS
+// and then scatters them in dense 64-column tiles.
+constexpr int kScatterSpan = 1024;
+
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
 k_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restrict__ r,
           const int32_t *__restrict__ id_slot, const typename ValT<V>::T *__restrict__ delta_slot,
           Ctrl *__restrict__ ctrl, int64_t tau)
 {
+    using T = typename ValT<V>::T;
+    __shared__ int32_t s_id[kScatterSpan];
+    __shared__ T s_d[kScatterSpan];
+    __shared__ int s_cnt;
     if (blockIdx.x == 0 && threadIdx.x == 0)
         ctrl->k += 1;  // no block of this kernel reads k
     const TileLanes<G> tl;
-    for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64)
-        scatter_tile<V, G>(seg, lay, r, id_slot, delta_slot, tl, base, tau);
+    const int wave = threadIdx.x >> 6;
+    for (int64_t base = (int64_t)blockIdx.x * kScatterSpan; base < tau; base += (int64_t)gridDim.x * kScatterSpan) {
+        if (threadIdx.x == 0)
+            s_cnt = 0;
+        __syncthreads();
+        for (int j = threadIdx.x; j < kScatterSpan; j += kBlock) {
+            const int64_t slot = base + j;
+            if (slot < tau) {
+                const T d = delta_slot[slot];
+                if (d != T(0)) {
+                    const int q = atomicAdd(&s_cnt, 1);
+                    s_id[q] = id_slot[slot];
+                    s_d[q] = d;
+                }
+            }
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        for (int t0 = wave * 64; t0 < cnt; t0 += kBlock) {
+            const int e = t0 + tl.lane;
+            const bool live = e < cnt;
+            const T d = live ? s_d[e] : T(0);
+            int64_t off = 0;
+            int32_t dp = 0;
+            if (live)
+                locate<V>(lay, s_id[e], off, dp);
+            tile_entries<V, G>(seg, tl, off, dp, d, [&](int, T dq, int row, T val) {
+                if (val != T(0))
+                    atomic_add_hw<T>(r + row, dq * val);
+            });
+        }
+        __syncthreads();
+    }
 }
 
 // --------------------------------------------------------------------------

@@ -449,8 +449,9 @@ template <typename V> struct Ops {
                            (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part,
                            P->seed, P->tau, (uint32_t)P->n, 1.0 / P->beta, prox_params(P), slot_plan(P));
         clock_stop(P, CLK_GATHER, t0, s);
+        const int sgrid = grid_for(P->tau, kScatterSpan, P->nblk_max);
         hipEvent_t t1 = clock_start(P, s);
-        hipLaunchKernelGGL((k_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+        hipLaunchKernelGGL((k_scatter<V, G>), dim3(sgrid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
                            (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl,
                            P->tau);
         clock_stop(P, CLK_SCATTER, t1, s);
