@@ -78,3 +78,73 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_new_entry_points_reject_null_and_bad_arguments():
+    """Argument checks that run on the host, before any device work."""
+    lib = pc.load()
+    assert lib.pcdm_step_async(None, 1, None) == _lib.PCDM_EINVAL
+    assert lib.pcdm_set_slot_mask(None, None, 0, 0, None) == _lib.PCDM_EINVAL
+    assert lib.pcdm_sample_draw(3, 1.0, 0, 0, 4, 10, 8, None) == _lib.PCDM_EINVAL       # unknown sampling
+    assert lib.pcdm_sample_draw(2, 0.0, 0, 0, 4, 10, 8, None) == _lib.PCDM_EINVAL       # p_b out of (0, 1]
+    assert lib.pcdm_sample_draw(1, 1.0, 0, 0, 4, 10, None, None) == _lib.PCDM_EINVAL    # no output
+    d, keep = _desc()
+    b = np.zeros(4)
+    h = ctypes.c_void_p(1234)
+    assert lib.pcdm_create_model(ctypes.byref(d), b.ctypes.data, None, 1, 0, ctypes.byref(h)) == _lib.PCDM_EINVAL
+    assert h.value is None
+
+
+@pytest.mark.parametrize("loss,scale,l1,l2,lin,lo,hi", [
+    (3, 1.0, 0.0, 0.0, 0.0, -np.inf, np.inf),          # unknown loss
+    (0, 0.0, 0.0, 0.0, 0.0, -np.inf, np.inf),          # scale must be > 0
+    (0, np.inf, 0.0, 0.0, 0.0, -np.inf, np.inf),
+    (0, 1.0, -0.1, 0.0, 0.0, -np.inf, np.inf),         # negative l1
+    (1, 1.0, 0.0, -1.0, 0.0, -np.inf, np.inf),         # negative l2
+    (2, 1.0, 0.0, 0.0, np.nan, -np.inf, np.inf),       # linear term not finite
+    (0, 1.0, 0.0, 0.0, 0.0, 0.5, 1.0),                 # box must contain 0
+    (0, 1.0, 0.0, 0.0, 0.0, -1.0, -0.5),
+])
+def test_create_model_rejects_bad_terms(loss, scale, l1, l2, lin, lo, hi):
+    lib = pc.load()
+    d, keep = _desc()
+    b = np.zeros(4)
+    mdl = _lib.pcdm_model(loss, 0, scale, l1, l2, lin, lo, hi)
+    h = ctypes.c_void_p(1234)
+    assert lib.pcdm_create_model(ctypes.byref(d), b.ctypes.data, ctypes.byref(mdl), 1, 0,
+                                 ctypes.byref(h)) == _lib.PCDM_EINVAL
+    assert h.value is None
+    assert lib.pcdm_last_error()
+
+
+@pytest.mark.parametrize("bp,tau", [
+    ([0, 1, 2, 3], 0), ([0, 1, 2, 3], 4),     # tau outside [1, nblocks]
+    ([1, 2, 3, 3], 1),                        # does not start at 0
+    ([0, 1, 2, 2], 1),                        # empty block
+    ([0, 2, 1, 3], 1),                        # decreasing
+    ([0, 1, 2], 1),                           # ends before n (n = 3, two blocks cover 2 columns)
+])
+def test_create_group_rejects_bad_blocks(bp, tau):
+    lib = pc.load()
+    d, keep = _desc()
+    b = np.zeros(4)
+    bpa = np.array(bp, dtype=np.int64)
+    h = ctypes.c_void_p(1234)
+    st = lib.pcdm_create_group(ctypes.byref(d), b.ctypes.data, 0.1, bpa.ctypes.data, bpa.size - 1, tau, 0,
+                               ctypes.byref(h))
+    assert st == _lib.PCDM_EINVAL
+    assert h.value is None
+
+
+def test_create_group_rejects_blocks_over_sixteen_columns():
+    lib = pc.load()
+    n = 20
+    cp = np.arange(n + 1, dtype=np.int64)
+    ri = np.zeros(n, dtype=np.int32)
+    v = np.ones(n)
+    d = _lib.pcdm_csc(4, n, n, cp.ctypes.data, ri.ctypes.data, v.ctypes.data, _lib.PCDM_F64, 0)
+    bpa = np.array([0, 17, 20], dtype=np.int64)
+    h = ctypes.c_void_p(1234)
+    assert lib.pcdm_create_group(ctypes.byref(d), np.zeros(4).ctypes.data, 0.1, bpa.ctypes.data, 2, 1, 0,
+                                 ctypes.byref(h)) == _lib.PCDM_EINVAL
+    assert b"16" in lib.pcdm_last_error()
