@@ -37,7 +37,7 @@ def _sparse(A):
     return sp.csc_matrix((A.values_f64(), A.row_idx, A.col_ptr), shape=(A.m, A.n))
 
 
-@pytest.mark.parametrize("dtype,lanes", [("f64", 0), ("f64", 1), ("f64", 64), ("f32", 0)])
+@pytest.mark.parametrize("dtype,lanes", [("f64", 0), ("f64", 1), ("f64", 64), ("f32", 0), ("bf16", 8)])
 def test_one_processor_is_the_serial_pick_stream(pc, dtype, lanes):
     rng = np.random.default_rng(31)
     A = random_csc_ragged(300, 500, 1, 30, rng, dtype=dtype)
@@ -65,6 +65,7 @@ def test_one_processor_is_the_serial_pick_stream(pc, dtype, lanes):
 @pytest.mark.parametrize("dtype,reads,rounds,procs", [
     ("f64", 0, 0, 0), ("f64", 1, 0, 0), ("f64", 2, 0, 0), ("f32", 0, 1, 0), ("f32", 2, 0, 0),
     ("f64", 0, 0, 300), ("f64", 1, 0, 300), ("f64", 2, 0, 300), ("f32", 0, 0, 300), ("f64", 0, 0, 5000),
+    ("bf16", 1, 0, 300), ("bf16", 0, 4, 0),
 ])
 def test_no_update_is_lost(pc, dtype, reads, rounds, procs):
     """Many processors, refresh off: the residual the atomics maintained equals
@@ -91,7 +92,7 @@ def test_no_update_is_lost(pc, dtype, reads, rounds, procs):
         r = p.get_residual()
     assert np.all(np.isfinite(x))
     recomputed = S @ x - inst.b
-    tol = 1e-12 if dtype == "f64" else 2e-5
+    tol = 1e-12 if dtype == "f64" else 2e-5   # bf16 values are exact in float32: same bar
     assert np.max(np.abs(r - recomputed)) <= tol * max(1.0, np.max(np.abs(inst.b)))
 
 
