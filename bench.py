@@ -198,6 +198,67 @@ def copy_bandwidth_gbps(nbytes: int = 1 << 30, reps: int = 10) -> float:
     return 2.0 * nbytes * reps / dt / 1e9
 
 
+def random_gather_ceiling(m: int, nthreads: int = 1_000_000, reps: int = 20) -> Optional[dict]:
+    """Rate of independent random 4-byte reads from a table of m floats (the
+    size of the residual), measured with the calibration kernel of
+    libpcdm_calib.so: the ceiling of the random-line requests that the
+    gathers of a coordinate step issue.  HIP events on the launch stream."""
+    import ctypes
+    import torch
+    from paper_1212_0873_amd import build as hipbuild
+    if not os.path.exists(hipbuild.CALIB_LIB):
+        return None
+    lib = ctypes.CDLL(hipbuild.CALIB_LIB)
+    lib.pcdm_calib_random_gather.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+    lib.pcdm_calib_random_gather.restype = ctypes.c_int
+    reads = int(lib.pcdm_calib_reads_per_thread())
+    table = torch.rand(m, dtype=torch.float32, device="cuda")
+    out = torch.empty(nthreads, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+
+    def launch(salt):
+        rc = lib.pcdm_calib_random_gather(table.data_ptr(), m, nthreads, salt, out.data_ptr(), sptr)
+        if rc != 0:
+            raise RuntimeError(f"pcdm_calib_random_gather failed: {rc}")
+
+    for k in range(3):
+        launch(k)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(reps):
+        launch(100 + k)
+    e1.record(stream)
+    e1.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    del table, out
+    torch.cuda.empty_cache()
+    return {"table_bytes": 4 * m, "reads_per_launch": nthreads * reads, "avg_launch_us": dt * 1e6,
+            "reads_per_s": nthreads * reads / dt}
+
+
+def read_l2_counters(kernel: str, workload: str, dtype: str, tau: int) -> Optional[dict]:
+    """L2 request counters per launch from a committed rocprofv3 summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_l2_{kernel}_{WORKLOAD_NAMES[workload]}_{dtype}_tau{tau}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.strip().split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return {k: float(kv[k]) for k in ("tcc_req_per_launch", "tcc_hit_per_launch", "tcc_miss_per_launch",
+                                          "calib_tcc_req_per_read")}
+    except (KeyError, ValueError):
+        return None
+
+
 def gpu_clocks() -> Optional[str]:
     """Current clock levels as rocm-smi reports them (best effort)."""
     import subprocess
@@ -707,6 +768,17 @@ def main() -> int:
     step_alg_bytes = b_gather * updates + b_scatter * nz
     workload = WORKLOAD_NAMES[args.config]
     traffic = read_traffic("gather", args.config, args.dtype, tau)
+    ceiling = random_gather_ceiling(A.m)
+    l2c = read_l2_counters("gather", args.config, args.dtype, tau)
+    l2 = {"random_read_ceiling": ceiling, "requests_per_launch": None, "hit_rate": None,
+          "request_rate_per_s": None, "frac_of_random_ceiling": None}
+    if l2c:
+        rate = l2c["tcc_req_per_launch"] / gather_avg_s
+        l2.update({"requests_per_launch": l2c["tcc_req_per_launch"],
+                   "hit_rate": l2c["tcc_hit_per_launch"] / l2c["tcc_req_per_launch"],
+                   "request_rate_per_s": rate})
+        if ceiling:
+            l2["frac_of_random_ceiling"] = rate / (ceiling["reads_per_s"] * l2c["calib_tcc_req_per_read"])
 
     out = {
         "metric": METRIC,
@@ -734,7 +806,8 @@ def main() -> int:
                      "measured_over_algorithmic": (traffic / gather_bytes) if traffic else None,
                      "copy_gbps": copy_gbps,
                      "frac_of_copy": achieved / copy_gbps,
-                     "measured_frac_of_copy": (traffic / gather_avg_s / 1e9 / copy_gbps) if traffic else None},
+                     "measured_frac_of_copy": (traffic / gather_avg_s / 1e9 / copy_gbps) if traffic else None,
+                     "l2_requests": l2},
         "hbm_gbps_algorithmic_step": step_alg_bytes / t_el / 1e9,
         "nonzero_update_fraction": nz / updates,
         "kernel_ms": {"gather": gms, "scatter": sms, "refresh": rms,

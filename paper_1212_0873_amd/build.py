@@ -9,6 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcdm.so")
+# memory-system calibration kernels used by bench.py (not the method)
+CALIB_LIB = os.path.join(HERE, "libpcdm_calib.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no v_pk_*_f32 generated for ordinary float code.
@@ -23,15 +25,26 @@ def sources():
     return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every .hip source under csrc/ into libpcdm.so (always rebuilds)."""
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *sources(), "-o", tmp]
+def calib_sources():
+    d = os.path.join(CSRC, "calib")
+    return [os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith(".hip")]
+
+
+def _compile(srcs, out, verbose):
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = [HIPCC, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every .hip source directly under csrc/ into libpcdm.so and the
+    calibration kernels under csrc/calib/ into libpcdm_calib.so (always
+    rebuilds both)."""
+    _compile(sources(), LIB, verbose)
+    _compile(calib_sources(), CALIB_LIB, verbose)
     return LIB
 
 

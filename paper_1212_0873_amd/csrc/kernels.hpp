@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sampler.hpp"
 
 namespace pcdm {
@@ -39,19 +41,33 @@ namespace pcdm {
 constexpr int kBlock = 256;
 constexpr int kHeader = 16;  // bytes of {x_i, 1/L_i} in front of each column
 
+// Fixed-stride records are padded to a multiple of this many bytes: a 176-byte
+// record (20 float32 entries) at 64-byte alignment spans two 128-byte lines
+// instead of 2.25 on average (measured: gather 163 -> 161 us per 1e6-slot
+// step on the 1e6-row instance, for 9% more record memory).
+#ifndef PCDM_RECORD_ALIGN
+#define PCDM_RECORD_ALIGN 64
+#endif
+
 // Column chunks (4 entries) a gather lane keeps in flight before its first
 // dependent r load: more hides latency, fewer leaves registers for more waves.
 #ifndef PCDM_CHUNK_BUDGET
 #define PCDM_CHUNK_BUDGET 8
 #endif
-// 1: column records are read with non-temporal loads (streamed past the
-// caches, which then keep r).
 // Column entries are read with the non-temporal hint: each sampled record is
 // used once per step, and keeping it out of the way leaves more of L2 to r
 // (measured: gather 168.7 -> 163.4 us per 1e6-slot step on the 1e6-row
 // instance).
 #ifndef PCDM_NT_RECORDS
 #define PCDM_NT_RECORDS 1
+#endif
+// 1: in the tiles, a lane of each column's group that holds no entries reads
+// the record header {x_i, 1/L_i} in the same load instruction as the rows,
+// instead of the owner lane reading it separately: one L2 request less per
+// column, and the header's registers are not held across the rounds
+// (measured: gather 161 -> 150 us per 1e6-slot step on the 1e6-row instance).
+#ifndef PCDM_HDR_FOLD
+#define PCDM_HDR_FOLD 1
 #endif
 
 typedef int v4i_t __attribute__((ext_vector_type(4)));
@@ -123,26 +139,38 @@ __device__ __forceinline__ void locate(const Layout &L, int64_t i, int64_t &off,
 // Load entries e..e+3 of a column whose rows start at `rows` (e a multiple of 4).
 template <typename V> struct Chunk4;
 
+// For float and double, `bits16` reads 16 aligned bytes (four rows, or a
+// record header) and `vals` the values of entries e..e+3.
 template <> struct Chunk4<float> {
+    __device__ __forceinline__ static v4i_t bits16(const char *p) { return ld_rec(reinterpret_cast<const v4i_t *>(p)); }
+    __device__ __forceinline__ static void vals(const char *rows, int32_t dpad, int32_t e, float (&v)[4])
+    {
+        const v4f_t b = ld_rec(reinterpret_cast<const v4f_t *>(rows + 4 * dpad + 4 * e));
+        v[0] = b.x; v[1] = b.y; v[2] = b.z; v[3] = b.w;
+    }
     __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
                                                 float (&v)[4])
     {
-        const v4i_t a = ld_rec(reinterpret_cast<const v4i_t *>(rows + 4 * e));
-        const v4f_t b = ld_rec(reinterpret_cast<const v4f_t *>(rows + 4 * dpad + 4 * e));
+        const v4i_t a = bits16(rows + 4 * e);
+        vals(rows, dpad, e, v);
         rw[0] = a.x; rw[1] = a.y; rw[2] = a.z; rw[3] = a.w;
-        v[0] = b.x; v[1] = b.y; v[2] = b.z; v[3] = b.w;
     }
 };
 
 template <> struct Chunk4<double> {
+    __device__ __forceinline__ static v4i_t bits16(const char *p) { return *reinterpret_cast<const v4i_t *>(p); }
+    __device__ __forceinline__ static void vals(const char *rows, int32_t dpad, int32_t e, double (&v)[4])
+    {
+        const double2 b0 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e);
+        const double2 b1 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e + 16);
+        v[0] = b0.x; v[1] = b0.y; v[2] = b1.x; v[3] = b1.y;
+    }
     __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
                                                 double (&v)[4])
     {
-        const int4 a = *reinterpret_cast<const int4 *>(rows + 4 * e);
-        const double2 b0 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e);
-        const double2 b1 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e + 16);
+        const v4i_t a = bits16(rows + 4 * e);
+        vals(rows, dpad, e, v);
         rw[0] = a.x; rw[1] = a.y; rw[2] = a.z; rw[3] = a.w;
-        v[0] = b0.x; v[1] = b0.y; v[2] = b1.x; v[3] = b1.y;
     }
 };
 
@@ -351,11 +379,16 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
     double xi = 0.0, il = 0.0;
     if (act)
         live = draw_slot(sd, key, (uint32_t)slot, i);
+    // A column of at most 4(G-1) entries leaves its group's last lane idle:
+    // that lane reads the header with the rows (PCDM_HDR_FOLD).
+    constexpr bool kFold = PCDM_HDR_FOLD && !std::is_same<V, bf16s>::value && G >= 2;
     if (live) {
         locate<V>(lay, i, off, dp);
-        const double *hdr = reinterpret_cast<const double *>(seg + off);
-        xi = hdr[0];
-        il = hdr[1];
+        if (!kFold || dp > 4 * (G - 1)) {
+            const double *hdr = reinterpret_cast<const double *>(seg + off);
+            xi = hdr[0];
+            il = hdr[1];
+        }
     }
     // rounds in batches of RB so that at most PCDM_CHUNK_BUDGET chunks per lane are live
     constexpr int RB = (G < PCDM_CHUNK_BUDGET / C) ? G : (PCDM_CHUNK_BUDGET / C > 0 ? PCDM_CHUNK_BUDGET / C : 1);
@@ -373,8 +406,30 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
             qoff[qq] = __shfl(off, tl.owner(q));
             qdp[qq] = __shfl(dp, tl.owner(q));
             const char *rows = seg + qoff[qq] + kHeader;
+            if constexpr (kFold) {
+                // chunk 0: rows of entries 4gl..4gl+3, or the header on the idle last lane
+                const int e = 4 * tl.gl;
+                const bool hl = tl.gl == G - 1 && qdp[qq] > 0 && qdp[qq] <= 4 * (G - 1);
+                const bool ld = e < qdp[qq];
+                // the header lane keeps the header's bits in rw: its entries are idle
+                if (ld || hl) {
+                    const v4i_t a = Chunk4<V>::bits16(ld ? rows + 4 * e : seg + qoff[qq]);
+                    rw[qq][0][0] = a.x; rw[qq][0][1] = a.y; rw[qq][0][2] = a.z; rw[qq][0][3] = a.w;
+                } else {
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
+                    for (int t = 0; t < 4; ++t)
+                        rw[qq][0][t] = 0;
+                }
+                if (ld) {
+                    Chunk4<V>::vals(rows, qdp[qq], e, v[qq][0]);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        v[qq][0][t] = T(0);
+                }
+            }
+#pragma unroll
+            for (int c = kFold ? 1 : 0; c < C; ++c) {
                 const int e = 4 * (tl.gl + G * c);
                 if (e < qdp[qq]) {
                     Chunk4<V>::load(rows, qdp[qq], e, rw[qq][c], v[qq][c]);
@@ -390,6 +445,16 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
         T acc[RB];
 #pragma unroll
         for (int qq = 0; qq < RB; ++qq) {
+            if constexpr (kFold) {
+                const int q = q0 + qq;
+                const int hsrc = tl.leader_of_mine(q) + G - 1;
+                const int h0 = __shfl(rw[qq][0][0], hsrc), h1 = __shfl(rw[qq][0][1], hsrc);
+                const int h2 = __shfl(rw[qq][0][2], hsrc), h3 = __shfl(rw[qq][0][3], hsrc);
+                if (tl.lane / TileLanes<G>::CPR == q && dp <= 4 * (G - 1)) {
+                    xi = __hiloint2double(h1, h0);
+                    il = __hiloint2double(h3, h2);
+                }
+            }
             acc[qq] = T(0);
 #pragma unroll
             for (int c = 0; c < C; ++c) {

@@ -904,11 +904,14 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
         P->lay.pc = P->pc;
         if (!hc.nonuniform) {
             HIP_TRY(hipMemcpy(&P->lay.fixed_dpad, dpad, 8, hipMemcpyDeviceToHost));
-            P->lay.stride = kHeader + P->lay.fixed_dpad * (int64_t)(4 + vb);
+            const int64_t rec = kHeader + P->lay.fixed_dpad * (int64_t)(4 + vb);
+            P->lay.stride = (rec + PCDM_RECORD_ALIGN - 1) / PCDM_RECORD_ALIGN * PCDM_RECORD_ALIGN;
         }
     }
 
-    HIP_TRY(hipMalloc(&P->seg, (size_t)P->stored_nnz * (4 + vb) + (size_t)kHeader * A->n));
+    const size_t seg_bytes = P->lay.fixed_dpad ? (size_t)P->lay.stride * (size_t)A->n
+                                               : (size_t)P->stored_nnz * (4 + vb) + (size_t)kHeader * A->n;
+    HIP_TRY(hipMalloc(&P->seg, seg_bytes));
     HIP_TRY(hipMalloc(&P->x, (size_t)A->n * 8));
     HIP_TRY(hipMalloc(&P->r, (size_t)A->m * P->tbytes));
     HIP_TRY(hipMalloc(&P->r64, (size_t)A->m * 8));

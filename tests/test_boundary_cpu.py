@@ -148,3 +148,19 @@ def test_create_group_rejects_blocks_over_sixteen_columns():
     assert lib.pcdm_create_group(ctypes.byref(d), np.zeros(4).ctypes.data, 0.1, bpa.ctypes.data, 2, 1, 0,
                                  ctypes.byref(h)) == _lib.PCDM_EINVAL
     assert b"16" in lib.pcdm_last_error()
+
+
+def test_calibration_library_rejects_bad_sizes():
+    """The benchmark's random-read calibration kernel (separate library, not
+    part of the boundary) is built and checks its sizes before launching."""
+    from paper_1212_0873_amd import build as hipbuild
+    lib = ctypes.CDLL(hipbuild.CALIB_LIB)
+    f = lib.pcdm_calib_random_gather
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    fake = ctypes.c_void_p(16)  # never dereferenced: every case below fails its size check first
+    assert f(None, 10, 10, 0, fake, None) == 1
+    assert f(fake, 0, 10, 0, fake, None) == 1
+    assert f(fake, 1 << 32, 10, 0, fake, None) == 1
+    assert f(fake, 10, 0, 0, fake, None) == 1
+    assert lib.pcdm_calib_reads_per_thread() == 20
