@@ -32,8 +32,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 #include "sampler.hpp"
 
 namespace pcdm {
@@ -139,8 +137,8 @@ __device__ __forceinline__ void locate(const Layout &L, int64_t i, int64_t &off,
 // Load entries e..e+3 of a column whose rows start at `rows` (e a multiple of 4).
 template <typename V> struct Chunk4;
 
-// For float and double, `bits16` reads 16 aligned bytes (four rows, or a
-// record header) and `vals` the values of entries e..e+3.
+// `bits16` reads 16 bytes (four rows, or a record header) and `vals` the
+// values of entries e..e+3.
 template <> struct Chunk4<float> {
     __device__ __forceinline__ static v4i_t bits16(const char *p) { return ld_rec(reinterpret_cast<const v4i_t *>(p)); }
     __device__ __forceinline__ static void vals(const char *rows, int32_t dpad, int32_t e, float (&v)[4])
@@ -174,18 +172,29 @@ template <> struct Chunk4<double> {
     }
 };
 
+// bf16 records are only 8-byte aligned in the variable-length layout, so 16
+// bytes are read as two 8-byte loads.
 template <> struct Chunk4<bf16s> {
-    __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
-                                                float (&v)[4])
+    __device__ __forceinline__ static v4i_t bits16(const char *p)
     {
-        const int2 a0 = *reinterpret_cast<const int2 *>(rows + 4 * e);
-        const int2 a1 = *reinterpret_cast<const int2 *>(rows + 4 * e + 8);
+        const int2 a0 = *reinterpret_cast<const int2 *>(p);
+        const int2 a1 = *reinterpret_cast<const int2 *>(p + 8);
+        return v4i_t{a0.x, a0.y, a1.x, a1.y};
+    }
+    __device__ __forceinline__ static void vals(const char *rows, int32_t dpad, int32_t e, float (&v)[4])
+    {
         const uint2 b = *reinterpret_cast<const uint2 *>(rows + 4 * dpad + 2 * e);
-        rw[0] = a0.x; rw[1] = a0.y; rw[2] = a1.x; rw[3] = a1.y;
         v[0] = __uint_as_float(b.x << 16);
         v[1] = __uint_as_float(b.x & 0xFFFF0000u);
         v[2] = __uint_as_float(b.y << 16);
         v[3] = __uint_as_float(b.y & 0xFFFF0000u);
+    }
+    __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
+                                                float (&v)[4])
+    {
+        const v4i_t a = bits16(rows + 4 * e);
+        vals(rows, dpad, e, v);
+        rw[0] = a.x; rw[1] = a.y; rw[2] = a.z; rw[3] = a.w;
     }
 };
 
@@ -381,7 +390,7 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
         live = draw_slot(sd, key, (uint32_t)slot, i);
     // A column of at most 4(G-1) entries leaves its group's last lane idle:
     // that lane reads the header with the rows (PCDM_HDR_FOLD).
-    constexpr bool kFold = PCDM_HDR_FOLD && !std::is_same<V, bf16s>::value && G >= 2;
+    constexpr bool kFold = PCDM_HDR_FOLD && G >= 2;
     if (live) {
         locate<V>(lay, i, off, dp);
         if (!kFold || dp > 4 * (G - 1)) {
@@ -1154,6 +1163,127 @@ k_atr_absmax(const char *__restrict__ seg, Layout lay, const double *__restrict_
                 mine = got;
         }
         best = fmax(best, fabs(mine));
+    }
+    best = block_max_f64(best, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = best;
+}
+
+// ||A^T r||_inf exactly, in two passes, for stored values of at most float32
+// precision.  Pass 1 (k_atr_bound) gathers t = fl32(r64), whose rows fit the
+// L2 of one XCD where r64 does not, and computes per column v_i = a_i^T t in
+// float64 with a bound E_i >= |a_i^T r64 (as the exact pass rounds it) - v_i|;
+// it writes ub_i >= |v_i| + E_i (float32, rounded up) and the largest
+// |v_i| - E_i.  Pass 2 (k_atr_exact) computes a_i^T r64 exactly as
+// k_atr_absmax does, but only for the columns with ub_i >= that lower bound:
+// every column attaining the maximum is among them, so the result is the
+// same number k_atr_absmax returns.
+//
+// Bound: t_j = r64_j rounded to nearest, so |r64_j - t_j| <= 2^-24 |t_j| +
+// 2^-150 (half an ulp, or half the least subnormal).  With g = sum |a_j t_j|,
+// s1 = sum |a_j| over the column's entries and gamma = (entries + 2) 2^-52
+// covering the float64 rounding of both passes' sums and of this bound's own
+// terms: E = (2^-24 g + 2^-149 s1 + 3 gamma g) (1 + 4 gamma).  A column whose
+// bound is not finite (NaN, or r beyond the float32 range) is always a
+// candidate.
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_atr_bound(const char *__restrict__ seg, Layout lay, const float *__restrict__ t32, int64_t n,
+            float *__restrict__ ub, double *__restrict__ part)
+{
+    using T = typename ValT<V>::T;
+    __shared__ double lds[kBlock];
+    const TileLanes<G> tl;
+    double best = 0.0;
+    for (int64_t base = wave_global_id() * 64; base < n; base += wave_count() * 64) {
+        const int64_t col = base + tl.lane;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (col < n)
+            locate<V>(lay, col, off, dp);
+        double acc[G], mag[G], s1[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            acc[q] = 0.0;
+            mag[q] = 0.0;
+            s1[q] = 0.0;
+        }
+        tile_entries<V, G>(seg, tl, off, dp, 0, [&](int q, int, int row, T val) {
+            const double pr = (double)val * (double)t32[row];
+            acc[q] += pr;
+            mag[q] += fabs(pr);
+            s1[q] += fabs((double)val);
+        });
+        double v = 0.0, g = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double sv = group_sum<G>(acc[q]), sg = group_sum<G>(mag[q]), sa = group_sum<G>(s1[q]);
+            const int src = tl.leader_of_mine(q);
+            const double gv = __shfl(sv, src), gg = __shfl(sg, src), ga = __shfl(sa, src);
+            if (tl.lane / TileLanes<G>::CPR == q) {
+                v = gv;
+                g = gg;
+                a1 = ga;
+            }
+        }
+        if (col < n) {
+            const double gam = (double)(dp + 2) * 0x1p-52;
+            const double E = (0x1p-24 * g + 0x1p-149 * a1 + 3.0 * gam * g) * (1.0 + 4.0 * gam);
+            // 2^-50 |v| covers the rounding of these last additions
+            const double hi = fabs(v) + E + 0x1p-50 * fabs(v);
+            float u = __builtin_inff();  // not finite (r beyond float32 range): always a candidate
+            if (hi < 3.0e38) {
+                u = (float)hi;
+                if ((double)u < hi)
+                    u = __int_as_float(__float_as_int(u) + 1);  // next float up (u >= 0, finite)
+                best = fmax(best, fabs(v) - E - 0x1p-50 * fabs(v));
+            }
+            ub[col] = u;
+        }
+    }
+    best = block_max_f64(best, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = best;
+}
+
+// Pass 2: max over the columns with ub_i >= *lo of |a_i^T r64|, each summed as
+// in k_atr_absmax.
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_atr_exact(const char *__restrict__ seg, Layout lay, const double *__restrict__ r64, int64_t n,
+            const float *__restrict__ ub, const double *__restrict__ lo, double *__restrict__ part)
+{
+    using T = typename ValT<V>::T;
+    __shared__ double lds[kBlock];
+    const TileLanes<G> tl;
+    const double thr = *lo;
+    double best = 0.0;
+    for (int64_t base = wave_global_id() * 64; base < n; base += wave_count() * 64) {
+        const int64_t col = base + tl.lane;
+        const bool cand = col < n && (double)ub[col] >= thr;
+        if (!__any(cand))
+            continue;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (cand)
+            locate<V>(lay, col, off, dp);
+        double acc[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            acc[q] = 0.0;
+        tile_entries<V, G>(seg, tl, off, dp, 0, [&](int q, int, int row, T val) {
+            acc[q] += (double)val * r64[row];
+        });
+        double mine = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double s = group_sum<G>(acc[q]);
+            const double got = __shfl(s, tl.leader_of_mine(q));
+            if (tl.lane / TileLanes<G>::CPR == q)
+                mine = got;
+        }
+        if (cand)
+            best = fmax(best, fabs(mine));
     }
     best = block_max_f64(best, lds);
     if (threadIdx.x == 0)

@@ -14,6 +14,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "group_kernels.hpp"
@@ -121,6 +122,9 @@ struct pcdm_problem {
     uint64_t *nz_part = nullptr;
     double *part = nullptr;   // kReduceBlocks * 3
     double *part2 = nullptr;  // nblk_max
+    float *t32 = nullptr;     // m: fl32(r64) for the bound pass of ||A^T r||_inf (values below float64)
+    float *ub = nullptr;      // n: per-column upper bounds of that pass
+    int max_passes = 2;       // ||A^T r||_inf: 2 = bound + exact pass where available, 1 = one exact pass
 
     int timing = 0;
     KernelClock clocks[CLK_COUNT];
@@ -199,7 +203,8 @@ void free_problem(pcdm_problem *P)
     for (hipEvent_t e : P->event_pool)
         (void)hipEventDestroy(e);
     void *bufs[] = {P->seg, P->pc, P->x, P->r, P->r64, P->b64, P->id_slot,
-                    P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim, P->bp, P->invlb, P->dx};
+                    P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim, P->bp, P->invlb, P->dx,
+                    P->t32, P->ub};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -666,12 +671,26 @@ template <typename V> struct Ops {
         hipLaunchKernelGGL((k_narrow<T>), dim3(gm), dim3(kBlock), 0, s, (const double *)P->r64, (T *)P->r, P->m);
     }
 
-    // ctrl->scal[3] = max_i |a_i^T rv|
+    // ctrl->scal[3] = max_i |a_i^T rv| (rv: device, m doubles).  Values of at
+    // most float32 precision take the two-pass route (a bound pass over
+    // fl32(rv), then the exact sums for the candidate columns only); it
+    // returns the same number as the single exact pass.
     static int atr_absmax(pcdm_problem *P, const double *rv, hipStream_t s)
     {
         const int grid = grid_for(P->n, kBlock, P->nblk_max);
-        hipLaunchKernelGGL((k_atr_absmax<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
-                           rv, P->n, P->part2);
+        if (std::is_same<V, double>::value || !P->t32 || !P->ub || P->max_passes == 1) {
+            hipLaunchKernelGGL((k_atr_absmax<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                               rv, P->n, P->part2);
+        } else {
+            const int gm = grid_for(P->m, kBlock, P->nblk_max);
+            hipLaunchKernelGGL((k_narrow<float>), dim3(gm), dim3(kBlock), 0, s, rv, P->t32, P->m);
+            hipLaunchKernelGGL((k_atr_bound<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                               (const float *)P->t32, P->n, P->ub, P->part2);
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
+                               P->ctrl->scal + 3);
+            hipLaunchKernelGGL((k_atr_exact<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                               rv, P->n, (const float *)P->ub, (const double *)(P->ctrl->scal + 3), P->part2);
+        }
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
                            P->ctrl->scal + 3);
         return PCDM_OK;
@@ -916,6 +935,10 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
     HIP_TRY(hipMalloc(&P->r, (size_t)A->m * P->tbytes));
     HIP_TRY(hipMalloc(&P->r64, (size_t)A->m * 8));
     HIP_TRY(hipMalloc(&P->b64, (size_t)A->m * 8));
+    if (P->dtype != PCDM_F64) {
+        HIP_TRY(hipMalloc(&P->t32, (size_t)A->m * 4));
+        HIP_TRY(hipMalloc(&P->ub, (size_t)A->n * 4));
+    }
     HIP_TRY(hipMemset(P->x, 0, (size_t)A->n * 8));
     HIP_TRY(hipMemcpy(P->b64, bdev, (size_t)A->m * 8, hipMemcpyDeviceToDevice));
     PCDM_TRY(ensure_slots(P, tau));
@@ -1278,6 +1301,10 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         if (!(value >= 0.0) || value > 4096.0 || value != std::floor(value))
             return fail(PCDM_EINVAL, "graph_steps must be an integer in [0, 4096]");
         h->graph_len = (int64_t)value;
+    } else if (k == "max_passes") {
+        if (value != 1.0 && value != 2.0)
+            return fail(PCDM_EINVAL, "max_passes must be 1 or 2");
+        h->max_passes = (int)value;
     } else if (k == "narrow_below") {
         if (!(value >= 0.0))
             return fail(PCDM_EINVAL, "narrow_below must be >= 0");
