@@ -229,6 +229,12 @@ k_group_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__
 
 // Phase 2: r += A_i dx^(i) for the sampled blocks that changed (slot id >= 0;
 // columns with dx != 0), hardware float atomics; advances the step counter.
+// Each workgroup first packs the changed columns of kGroupScatterSpan
+// consecutive slots into LDS as (column, dx) pairs, then scatters them in
+// dense 64-column tiles as the coordinate scatter does: late in a run few
+// blocks change, and a block's columns are no longer walked one after another.
+constexpr int kGroupScatterSpan = 128;
+
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
 k_group_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *__restrict__ r,
@@ -236,38 +242,51 @@ k_group_scatter(const char *__restrict__ seg, Layout lay, typename ValT<V>::T *_
                 const typename ValT<V>::T *__restrict__ dx, Ctrl *__restrict__ ctrl, int64_t tau)
 {
     using T = typename ValT<V>::T;
+    constexpr int kCap = kGroupScatterSpan * kGroupMax;
+    __shared__ int32_t s_col[kCap];
+    __shared__ T s_d[kCap];
+    __shared__ int s_cnt;
     if (blockIdx.x == 0 && threadIdx.x == 0)
         ctrl->k += 1;  // no block of this kernel reads k
-    constexpr int SPW = 64 / G;
-    const int lane = threadIdx.x & 63;
-    const int gl = lane & (G - 1);
-    for (int64_t base = wave_global_id() * SPW; base < tau; base += wave_count() * SPW) {
-        const int64_t slot = base + lane / G;
-        if (slot >= tau)
-            continue;
-        const int32_t i = id_slot[slot];
-        if (i < 0)
-            continue;  // block unchanged this step
-        const int64_t c0 = bp[i];
-        const int N = (int)(bp[i + 1] - c0);
-        for (int c = 0; c < N; ++c) {
-            const T d = dx[c0 + c];
-            if (d == T(0))
-                continue;
-            int64_t off;
-            int32_t dp;
-            locate<V>(lay, c0 + c, off, dp);
-            const char *rows = seg + off + kHeader;
-            for (int e = 4 * gl; e < dp; e += 4 * G) {
-                int rw[4];
-                T v[4];
-                Chunk4<V>::load(rows, dp, e, rw, v);
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (v[t] != T(0))
-                        atomic_add_hw<T>(r + rw[t], d * v[t]);
+    const TileLanes<G> tl;
+    const int wave = threadIdx.x >> 6;
+    for (int64_t base = (int64_t)blockIdx.x * kGroupScatterSpan; base < tau;
+         base += (int64_t)gridDim.x * kGroupScatterSpan) {
+        if (threadIdx.x == 0)
+            s_cnt = 0;
+        __syncthreads();
+        if (threadIdx.x < kGroupScatterSpan) {
+            const int64_t slot = base + threadIdx.x;
+            const int32_t i = slot < tau ? id_slot[slot] : -1;
+            if (i >= 0) {  // i < 0: block unchanged this step
+                const int64_t c0 = bp[i];
+                const int N = (int)(bp[i + 1] - c0);
+                for (int c = 0; c < N; ++c) {
+                    const T d = dx[c0 + c];
+                    if (d != T(0)) {
+                        const int q = atomicAdd(&s_cnt, 1);
+                        s_col[q] = (int32_t)(c0 + c);
+                        s_d[q] = d;
+                    }
+                }
             }
         }
+        __syncthreads();
+        const int cnt = s_cnt;
+        for (int t0 = wave * 64; t0 < cnt; t0 += kBlock) {
+            const int e = t0 + tl.lane;
+            const bool live = e < cnt;
+            const T d = live ? s_d[e] : T(0);
+            int64_t off = 0;
+            int32_t dp = 0;
+            if (live)
+                locate<V>(lay, s_col[e], off, dp);
+            tile_entries<V, G>(seg, tl, off, dp, d, [&](int, T dq, int row, T val) {
+                if (val != T(0))
+                    atomic_add_hw<T>(r + row, dq * val);
+            });
+        }
+        __syncthreads();
     }
 }
 

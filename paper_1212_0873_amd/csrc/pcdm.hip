@@ -539,7 +539,8 @@ template <typename V> struct Ops {
                            P->nz_part, P->seed, P->tau, (uint32_t)P->nb, 1.0 / P->beta, P->lambda);
         clock_stop(P, CLK_GATHER, t0, s);
         hipEvent_t t1 = clock_start(P, s);
-        hipLaunchKernelGGL((k_group_scatter<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+        const int sgrid = grid_for(P->tau, kGroupScatterSpan, P->nblk_max);
+        hipLaunchKernelGGL((k_group_scatter<V, G>), dim3(sgrid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
                            (T *)P->r, (const int64_t *)P->bp, (const int32_t *)P->id_slot, (const T *)P->dx, P->ctrl,
                            P->tau);
         clock_stop(P, CLK_SCATTER, t1, s);
