@@ -257,12 +257,13 @@ const char *pcdm_last_error(void);
  *                      refresh falls inside the run and "kernel_timing" is
  *                      off; the graph is rebuilt whenever an argument of the
  *                      step kernels changes (options, masks, sampling);
- *   "max_passes"       how ||A^T r||_inf (duality gap, ||A^T b||_inf) is
+ *   "max_passes"       how ||A^T r||_inf (duality gap, ||A^T b||_inf; for
+ *                      blocks max_i ||A_i^T r||_2) is
  *                      found for float32 / bf16 values: 2 (default) = a pass
- *                      over fl32(r) giving every column a rigorous bound,
- *                      then the exact float64 sums for the columns whose
- *                      bound reaches the largest lower bound; 1 = the exact
- *                      sums for every column.  Both give the same number;
+ *                      over fl32(r) giving every column (block) a rigorous
+ *                      bound, then the exact float64 sums for the columns
+ *                      (blocks) whose bound reaches the largest lower bound;
+ *                      1 = the exact sums everywhere.  Both give the same number;
  *                      float64 values always take one pass;
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"

@@ -308,23 +308,29 @@ k_group_xnorms(const int64_t *__restrict__ bp, int64_t nb, const double *__restr
 }
 
 // part[blk] = max over this block's share of the blocks of ||A_i^T r64||_2
-// (float64), a group of G lanes per block.
+// (float64), a group of G lanes per block.  With `ub` given, only the blocks
+// with ub[i] >= *lo are evaluated (the others count as 0); each evaluated
+// block's norm is summed exactly as without the filter.
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
 k_group_atr(const char *__restrict__ seg, Layout lay, const double *__restrict__ r64, const int64_t *__restrict__ bp,
-            int64_t nb, double *__restrict__ part)
+            int64_t nb, const float *__restrict__ ub, const double *__restrict__ lo, double *__restrict__ part)
 {
     using T = typename ValT<V>::T;
     __shared__ double lds[kBlock];
     constexpr int SPW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
+    const double thr = ub ? *lo : 0.0;
     double best = 0.0;
     for (int64_t base = wave_global_id() * SPW; base < nb; base += wave_count() * SPW) {
         const int64_t i = base + lane / G;
+        const bool cand = i < nb && (!ub || (double)ub[i] >= thr);
+        if (!__any(cand))
+            continue;
         int N = 0;
         int64_t c0 = 0;
-        if (i < nb) {
+        if (cand) {
             c0 = bp[i];
             N = (int)(bp[i + 1] - c0);
         }
@@ -349,6 +355,78 @@ k_group_atr(const char *__restrict__ seg, Layout lay, const double *__restrict__
             s2 += g * g;
         }
         best = fmax(best, sqrt(s2));
+    }
+    best = block_max_f64(best, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = best;
+}
+
+// Bound pass of max_i ||A_i^T r64||_2 for values of at most float32
+// precision, as for the coordinate maximum: each column's exact float64 dot
+// with r64 lies within E_c of its dot v_c with t = fl32(r64) (the bound of the
+// coordinate pass), so the block norm lies in
+// [sqrt(sum max(0, |v_c| - E_c)^2), sqrt(sum (|v_c| + E_c)^2)], widened by
+// 2^-40 relative for the rounding of the norms.  Writes the upper end to
+// ub[i] (float32, rounded up) and part[blk] = the largest lower end.
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_group_atr_bound(const char *__restrict__ seg, Layout lay, const float *__restrict__ t32,
+                  const int64_t *__restrict__ bp, int64_t nb, float *__restrict__ ub, double *__restrict__ part)
+{
+    using T = typename ValT<V>::T;
+    __shared__ double lds[kBlock];
+    constexpr int SPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    double best = 0.0;
+    for (int64_t base = wave_global_id() * SPW; base < nb; base += wave_count() * SPW) {
+        const int64_t i = base + lane / G;
+        int N = 0;
+        int64_t c0 = 0;
+        if (i < nb) {
+            c0 = bp[i];
+            N = (int)(bp[i + 1] - c0);
+        }
+        double hi2 = 0.0, lo2 = 0.0;
+        for (int c = 0; c < kGroupMax; ++c) {
+            if (c >= N)
+                break;
+            int64_t off;
+            int32_t dp;
+            locate<V>(lay, c0 + c, off, dp);
+            const char *rows = seg + off + kHeader;
+            double acc = 0.0, mag = 0.0, s1 = 0.0;
+            for (int e = 4 * gl; e < dp; e += 4 * G) {
+                int rw[4];
+                T v[4];
+                Chunk4<V>::load(rows, dp, e, rw, v);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double pr = (double)v[t] * (double)t32[rw[t]];
+                    acc += pr;
+                    mag += fabs(pr);
+                    s1 += fabs((double)v[t]);
+                }
+            }
+            const double vv = group_sum<G>(acc), g = group_sum<G>(mag), a1 = group_sum<G>(s1);
+            const double gam = (double)(dp + 2) * 0x1p-52;
+            const double E = (0x1p-24 * g + 0x1p-149 * a1 + 3.0 * gam * g) * (1.0 + 4.0 * gam) + 0x1p-50 * fabs(vv);
+            const double up = fabs(vv) + E, dn = fmax(0.0, fabs(vv) - E);
+            hi2 += up * up;
+            lo2 += dn * dn;
+        }
+        if (i < nb) {
+            const double hi = sqrt(hi2) * (1.0 + 0x1p-40);
+            float u = __builtin_inff();  // not finite (r beyond float32 range): always a candidate
+            if (hi < 3.0e38) {
+                u = (float)hi;
+                if ((double)u < hi)
+                    u = __int_as_float(__float_as_int(u) + 1);  // next float up (u >= 0, finite)
+                best = fmax(best, sqrt(lo2) * (1.0 - 0x1p-40));
+            }
+            if (gl == 0)
+                ub[i] = u;
+        }
     }
     best = block_max_f64(best, lds);
     if (threadIdx.x == 0)

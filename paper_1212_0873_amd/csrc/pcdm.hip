@@ -568,9 +568,22 @@ template <typename V> struct Ops {
                            (const double *)P->x, P->part2);
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, g, 1, 0, P->ctrl->scal + 2);
         if (gap) {
+            // max_i ||A_i^T r64||_2: two passes as for the coordinate maximum
+            // (bound over fl32(r64), exact norms of the candidate blocks), or one
             const int ga = grid_for(P->nb * 8, kBlock, P->nblk_max);
+            const bool two = !std::is_same<V, double>::value && P->t32 && P->ub && P->max_passes == 2;
+            if (two) {
+                const int gm = grid_for(P->m, kBlock, P->nblk_max);
+                hipLaunchKernelGGL((k_narrow<float>), dim3(gm), dim3(kBlock), 0, s, (const double *)P->r64, P->t32,
+                                   P->m);
+                hipLaunchKernelGGL((k_group_atr_bound<V, 8>), dim3(ga), dim3(kBlock), 0, s, (const char *)P->seg,
+                                   P->lay, (const float *)P->t32, (const int64_t *)P->bp, P->nb, P->ub, P->part2);
+                hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, ga, 1, 1,
+                                   P->ctrl->scal + 3);
+            }
             hipLaunchKernelGGL((k_group_atr<V, 8>), dim3(ga), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
-                               (const double *)P->r64, (const int64_t *)P->bp, P->nb, P->part2);
+                               (const double *)P->r64, (const int64_t *)P->bp, P->nb,
+                               two ? (const float *)P->ub : nullptr, (const double *)(P->ctrl->scal + 3), P->part2);
             hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, ga, 1, 1,
                                P->ctrl->scal + 3);
         }

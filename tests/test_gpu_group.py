@@ -166,3 +166,34 @@ def test_block_error_paths(pc):
         p.set_option("tau", 10)
         assert p.info()["beta"] == pytest.approx(oracle.beta_nice(p.info()["omega"], 10, 10))
         p.step(3)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gap_two_passes_equal_one(pc, dtype):
+    """The block-norm maximum of the group gap: bound pass over fl32(r) plus
+    exact norms of the candidate blocks gives the single pass's number.  x is
+    supported on blocks that share no row, so the float64 residual does not
+    depend on the order of the refresh's atomic adds."""
+    rng = np.random.default_rng(40)
+    A = random_csc(900, 600, 4, rng).astype(dtype)
+    b = rng.standard_normal(900) * 10.0 ** rng.uniform(-20, 20, 900)
+    bp = _random_blocks(600, rng, 1, 6)
+    used = np.zeros(900, dtype=bool)
+    x = np.zeros(600)
+    for i in rng.permutation(len(bp) - 1):
+        rows = np.concatenate([A.row_idx[A.col_ptr[c]:A.col_ptr[c + 1]] for c in range(bp[i], bp[i + 1])])
+        if not used[rows].any():
+            used[rows] = True
+            x[bp[i]:bp[i + 1]] = rng.standard_normal(bp[i + 1] - bp[i]).astype(np.float32)
+    out = {}
+    for passes in (1, 2):
+        with pc.Problem(A, b, 0.3, 5, seed=0, blocks=bp) as p:
+            p.set_option("max_passes", passes)
+            p.set_x(x)
+            out[passes] = p.objective(gap=True)
+    assert out[1] == out[2], out
+    ref = group.GroupSolver(A, b, 0.3, bp, tau=5, seed=0)
+    ref.x = x.copy()
+    gap_r, F_r, _ = ref.gap()
+    assert out[2][0] == pytest.approx(F_r, rel=1e-12)
+    assert out[2][1] == pytest.approx(gap_r, rel=1e-9, abs=1e-12 * abs(F_r))
