@@ -179,19 +179,74 @@ k_group_gather(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__
             scale = invl[i] * inv_beta;  // 1 / (beta L_i)
         }
         double u[kGroupMax], xs[kGroupMax];
-        double nrm2 = 0.0;
 #pragma unroll
         for (int c = 0; c < kGroupMax; ++c) {
             u[c] = 0.0;
             xs[c] = 0.0;
-            if (c < N) {
-                int64_t off;
-                int32_t dp;
-                locate<V>(lay, c0 + c, off, dp);
-                xs[c] = *reinterpret_cast<const double *>(seg + off);
-                const T g = group_sum<G>(lane_dot<V, G, 1>(seg + off + kHeader, dp, gl, r));
-                u[c] = xs[c] - (double)g * scale;
-                nrm2 += u[c] * u[c];
+        }
+        double nrm2 = 0.0;
+        // The block's columns in batches of CB: the record loads of a batch,
+        // then its r gathers, then its reductions, so that the loads of
+        // several columns are in flight together.  Each column is summed as
+        // lane_dot sums it (first chunk, then the remaining ones).
+        constexpr int CB = 4;
+#pragma unroll
+        for (int cb = 0; cb < kGroupMax; cb += CB) {
+            if (!__any(cb < N))
+                break;
+            int64_t off[CB];
+            int32_t dp[CB];
+            int rw[CB][4];
+            T v[CB][4];
+#pragma unroll
+            for (int q = 0; q < CB; ++q) {
+                const int c = cb + q;
+                off[q] = 0;
+                dp[q] = 0;
+                if (c < N) {
+                    locate<V>(lay, c0 + c, off[q], dp[q]);
+                    xs[c] = *reinterpret_cast<const double *>(seg + off[q]);
+                }
+                if (4 * gl < dp[q]) {
+                    Chunk4<V>::load(seg + off[q] + kHeader, dp[q], 4 * gl, rw[q], v[q]);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        rw[q][t] = 0;
+                        v[q][t] = T(0);
+                    }
+                }
+            }
+            T acc[CB];
+#pragma unroll
+            for (int q = 0; q < CB; ++q) {
+                acc[q] = T(0);
+                if (4 * gl < dp[q]) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[q] += v[q][t] * load_row(r, rw[q][t]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < CB; ++q) {
+                const char *rows = seg + off[q] + kHeader;
+                for (int e = 4 * (gl + G); e < dp[q]; e += 4 * G) {
+                    int rr[4];
+                    T vv[4];
+                    Chunk4<V>::load(rows, dp[q], e, rr, vv);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[q] += vv[t] * load_row(r, rr[t]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < CB; ++q) {
+                const int c = cb + q;
+                if (c < N) {
+                    const T g = group_sum<G>(acc[q]);
+                    u[c] = xs[c] - (double)g * scale;
+                    nrm2 += u[c] * u[c];
+                }
             }
         }
         const double nrm = sqrt(nrm2);
