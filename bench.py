@@ -199,10 +199,11 @@ def copy_bandwidth_gbps(nbytes: int = 1 << 30, reps: int = 10) -> float:
 
 
 def random_gather_ceiling(m: int, nthreads: int = 1_000_000, reps: int = 20) -> Optional[dict]:
-    """Rate of independent random 4-byte reads from a table of m floats (the
-    size of the residual), measured with the calibration kernel of
-    libpcdm_calib.so: the ceiling of the random-line requests that the
-    gathers of a coordinate step issue.  HIP events on the launch stream."""
+    """Rates of independent random 4-byte reads and of random float atomic
+    adds on a table of m floats (the size of the residual), measured with the
+    calibration kernels of libpcdm_calib.so: the ceilings of the random-line
+    requests that the gathers and the scatter of a coordinate step issue.
+    HIP events on the launch stream."""
     import ctypes
     import torch
     from paper_1212_0873_amd import build as hipbuild
@@ -223,19 +224,33 @@ def random_gather_ceiling(m: int, nthreads: int = 1_000_000, reps: int = 20) -> 
         if rc != 0:
             raise RuntimeError(f"pcdm_calib_random_gather failed: {rc}")
 
-    for k in range(3):
-        launch(k)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for k in range(reps):
-        launch(100 + k)
-    e1.record(stream)
-    e1.synchronize()
-    dt = e0.elapsed_time(e1) / 1e3 / reps
+    lib.pcdm_calib_random_atomic.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
+                                             ctypes.c_void_p]
+    lib.pcdm_calib_random_atomic.restype = ctypes.c_int
+
+    def launch_atomic(salt):
+        rc = lib.pcdm_calib_random_atomic(table.data_ptr(), m, nthreads, salt, sptr)
+        if rc != 0:
+            raise RuntimeError(f"pcdm_calib_random_atomic failed: {rc}")
+
+    def timed(fn):
+        for k in range(3):
+            fn(k)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(reps):
+            fn(100 + k)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    dt = timed(launch)
+    dta = timed(launch_atomic)
     del table, out
     torch.cuda.empty_cache()
     return {"table_bytes": 4 * m, "reads_per_launch": nthreads * reads, "avg_launch_us": dt * 1e6,
-            "reads_per_s": nthreads * reads / dt}
+            "reads_per_s": nthreads * reads / dt, "atomic_avg_launch_us": dta * 1e6,
+            "atomics_per_s": nthreads * reads / dta}
 
 
 def read_l2_counters(kernel: str, workload: str, dtype: str, tau: int) -> Optional[dict]:
@@ -636,6 +651,59 @@ def run_group(args) -> int:
     return 0
 
 
+def run_adjoint(args) -> int:
+    """The differentiation pattern on the 1e5 x 1e6 training matrix (10
+    nonzeros per column, tau = 4096): forward solve from x = 0 to a certified
+    1e-6 gap, then d loss/d b and d loss/d lambda of the validation loss
+    ||V (x - x*)||^2 (V: 2e4 x 1e6, 10 nonzeros per column) through the
+    solution by pcdm_grad_backward; forward and adjoint wall times (HIP
+    synchronised), float32 and float64 values."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import make_config, random_csc
+
+    torch.cuda.set_device(0)
+    res = {}
+    for dtype in ("f32", "f64"):
+        inst = make_config("train_1e5x1e6", dtype=dtype, tau=4096)
+        rng = np.random.default_rng(3)
+        Vc = random_csc(20000, inst.A.n, 10, rng, normalize=False)
+        V = sp.csc_matrix((Vc.values_f64(), Vc.row_idx, Vc.col_ptr), shape=(Vc.m, Vc.n))
+        with pc.Problem(inst.A, inst.b, inst.lam, 4096, seed=2) as p:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = p.solve(rel_gap=1e-6, check_every=5)
+            torch.cuda.synchronize()
+            t_fwd = time.perf_counter() - t0
+            x = p.get_x()
+            e = V @ (x - inst.xstar)
+            g = torch.from_numpy(2.0 * (V.T @ e)).cuda()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            converged = True
+            try:
+                db, dl = p.grad_backward(g)
+            except pc.PCDMError:
+                converged = False
+                dl = None
+            torch.cuda.synchronize()
+            t_adj = time.perf_counter() - t1
+        res[dtype] = {"forward_seconds": t_fwd, "forward_epochs": st["epochs"], "forward_rel_gap": st["rel_gap"],
+                      "support": int(np.count_nonzero(x)), "adjoint_seconds": t_adj,
+                      "adjoint_converged": converged, "adjoint_over_forward": t_adj / t_fwd,
+                      "dL_dlambda": dl, "validation_loss": float(e @ e)}
+        print(f"[bench] adjoint {dtype}: {res[dtype]}", file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "mode": "adjoint", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "train_1e5x1e6_d10", "tau": 4096, "validation": "2e4 x 1e6, d = 10",
+                      "forward_target_rel_gap": 1e-6},
+           "results": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -651,13 +719,15 @@ def main() -> int:
     ap.add_argument("--gap-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models", "path", "group"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models", "path", "group",
+                             "adjoint"],
                     help="single: one instance (default); batched: the uneven lambda path; "
                          "dtypes: time to gap with float64 / float32 / bf16 values; taus: tau sweep "
                          "on both 1e7-column instances; samplings: nice / independent / binomial / "
                          "masked slots; async: asynchronous variant vs synchronous steps; models: "
                          "logistic regression and the SVM dual; path: warm-started regularisation path; "
-                         "group: group LASSO with blocks of 4 columns")
+                         "group: group LASSO with blocks of 4 columns; adjoint: forward solve and "
+                         "d loss/d (b, lambda) on the training matrix")
     ap.add_argument("--count", type=int, default=64, help="problems in the batched mode")
     ap.add_argument("--check-steps", type=int, default=64, help="batched mode: steps between gap checks")
     args = ap.parse_args()
@@ -686,6 +756,8 @@ def main() -> int:
         return run_path(args)
     if args.mode == "group":
         return run_group(args)
+    if args.mode == "adjoint":
+        return run_adjoint(args)
 
     import numpy as np
     import torch
@@ -808,6 +880,10 @@ def main() -> int:
                      "frac_of_copy": achieved / copy_gbps,
                      "measured_frac_of_copy": (traffic / gather_avg_s / 1e9 / copy_gbps) if traffic else None,
                      "l2_requests": l2},
+        "scatter_atomics": {"atomics": nz * d_avg, "per_s": nz * d_avg / max(sms / 1e3, 1e-12),
+                            "frac_of_random_atomic_ceiling":
+                                (nz * d_avg / max(sms / 1e3, 1e-12) / ceiling["atomics_per_s"]) if ceiling else None,
+                            "note": "nonzero updates x mean column length over the summed scatter launch time"},
         "hbm_gbps_algorithmic_step": step_alg_bytes / t_el / 1e9,
         "nonzero_update_fraction": nz / updates,
         "kernel_ms": {"gather": gms, "scatter": sms, "refresh": rms,

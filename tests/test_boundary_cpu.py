@@ -164,3 +164,9 @@ def test_calibration_library_rejects_bad_sizes():
     assert f(fake, 1 << 32, 10, 0, fake, None) == 1
     assert f(fake, 10, 0, 0, fake, None) == 1
     assert lib.pcdm_calib_reads_per_thread() == 20
+    g = lib.pcdm_calib_random_atomic
+    g.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p]
+    g.restype = ctypes.c_int
+    assert g(None, 10, 10, 0, None) == 1
+    assert g(fake, 0, 10, 0, None) == 1
+    assert g(fake, 10, -1, 0, None) == 1

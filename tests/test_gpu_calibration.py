@@ -1,6 +1,7 @@
-"""The benchmark's random-read calibration kernel (libpcdm_calib.so) reads
-exactly the positions it documents: each thread's output equals the sum of the
-20 table entries picked by its fmix32 chain, recomputed on the host."""
+"""The benchmark's calibration kernels (libpcdm_calib.so) touch exactly the
+positions they document: each thread's output of the random-read kernel is
+the sum of the 20 table entries its fmix32 chain picks, and the random-atomic
+kernel adds 1 at each of those picks, both recomputed on the host."""
 
 import ctypes
 
@@ -47,3 +48,25 @@ def test_calibration_reads_the_documented_positions():
                 acc += float(table[int(h) % m])
             want[t] = acc
         np.testing.assert_array_equal(got.astype(np.float64), want)
+
+
+def test_calibration_atomics_hit_the_documented_positions():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1212_0873_amd import build as hipbuild
+    lib = ctypes.CDLL(hipbuild.CALIB_LIB)
+    f = lib.pcdm_calib_random_atomic
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    reads = lib.pcdm_calib_reads_per_thread()
+    m, nthreads, salt = 997, 500, 42
+    tab = torch.zeros(m, dtype=torch.float32, device="cuda")
+    assert f(tab.data_ptr(), m, nthreads, salt, None) == 0
+    torch.cuda.synchronize()
+    want = np.zeros(m)
+    for t in range(nthreads):
+        h = _fmix32(np.uint32(t) ^ np.uint32(salt))
+        for q in range(reads):
+            h = _fmix32(np.uint32((int(h) + q) & 0xFFFFFFFF))
+            want[int(h) % m] += 1.0
+    np.testing.assert_array_equal(tab.cpu().numpy().astype(np.float64), want)
