@@ -126,6 +126,13 @@ typedef struct pcdm_info {
  * of range, non-finite values, a malformed col_ptr.  x starts at 0 and
  * r = -b.  Runs on the default stream and returns after the device work is
  * complete.  On failure *out is set to NULL.
+ * Device memory held by the handle: the column records (16 bytes per column
+ * plus the column's entries padded to a multiple of 4, each 4 + sizeof(value)
+ * bytes; with equal column lengths every record is padded to 64 bytes),
+ * 8 (n + 1) bytes of column pointers, x (8 n), r (m * sizeof(working type)),
+ * r64 and b (8 m each), per-slot results (tau * (4 + sizeof(working type)))
+ * and, for float32 / bf16 values, 4 (m + n) bytes for the two-pass
+ * ||A^T r||_inf (option "max_passes").
  */
 int pcdm_create(const pcdm_csc *A, const double *b, double lambda, int64_t tau,
                 uint64_t seed, pcdm_problem **out);
