@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests are skipped, not failed, where no GPU is visible; on a GPU machine
+    # GPU tests are skipped, not failed, where no GPU is visible; on a machine with one
     # they run against the in-tree HIP library, which must load.
     try:
         import torch
