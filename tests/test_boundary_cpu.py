@@ -170,3 +170,18 @@ def test_calibration_library_rejects_bad_sizes():
     assert g(None, 10, 10, 0, None) == 1
     assert g(fake, 0, 10, 0, None) == 1
     assert g(fake, 10, -1, 0, None) == 1
+
+
+def test_every_option_key_is_documented():
+    """The keys pcdm_set_option accepts are exactly the keys its comment in
+    include/pcdm.h documents."""
+    src = open(os.path.join(ROOT, "paper_1212_0873_amd", "csrc", "pcdm.hip")).read()
+    start = src.index("int pcdm_set_option(pcdm_problem *h, const char *key, double value)\n{")
+    body = src[start:src.index("\n}\n", start)]
+    accepted = set(re.findall(r'k == "([a-z_0-9]+)"', body))
+    hdr = open(os.path.join(ROOT, "include", "pcdm.h")).read()
+    end = hdr.index("int pcdm_set_option(pcdm_problem *h, const char *key, double value);")
+    block = hdr[hdr.rindex("/*", 0, end):end]
+    documented = set(re.findall(r'"([a-z_0-9]+)"', block))
+    assert accepted == documented, (accepted - documented, documented - accepted)
+
