@@ -328,6 +328,27 @@ def c2_full():
     return make_config("lasso_1e6x1e7", dtype="f32", tau=1_000_000)
 
 
+def test_full_size_exact_max_routes_agree(pc, c2_full):
+    """1e6 x 1e7: ||A^T b||_inf and the gap at x = 0 (r = -b exactly, no
+    atomics) are the same numbers by the two-pass and the single-pass route;
+    after steps the two routes agree to the float64 refresh's rounding."""
+    inst = c2_full
+    with pc.Problem(inst.A, inst.b, inst.lam, 1_000_000, seed=0) as p:
+        atb2 = p.info()["atb_inf"]  # at create: two passes
+        F2, g2 = p.objective(gap=True)
+        p.set_option("max_passes", 1)
+        p.set_rhs(inst.b)
+        atb1 = p.info()["atb_inf"]
+        F1, g1 = p.objective(gap=True)
+        assert (atb1, F1, g1) == (atb2, F2, g2)
+        p.step(30)
+        F1, g1 = p.objective(gap=True)
+        p.set_option("max_passes", 2)
+        F2, g2 = p.objective(gap=True)
+    assert F2 == pytest.approx(F1, rel=1e-13)
+    assert g2 == pytest.approx(g1, rel=1e-10)
+
+
 def test_full_size_steps_match_oracle(pc, c2_full):
     """Three steps of tau = 1e6 on the 1e6 x 1e7 (2e8 nnz) instance: every x_i
     and F against the oracle on the same float32-stored matrix."""
