@@ -54,8 +54,8 @@ constexpr int kHeader = 16;  // bytes of {x_i, 1/L_i} in front of each column
 #endif
 // Column entries are read with the non-temporal hint: each sampled record is
 // used once per step, and keeping it out of the way leaves more of L2 to r
-// (measured: gather 168.7 -> 163.4 us per 1e6-slot step on the 1e6-row
-// instance).
+// (measured, gather per 1e6-slot step on the 1e6-row instance: float32
+// 168.7 -> 163.4 us, bf16 163.8 -> 159.4 us, float64 224.9 -> 219.5 us).
 #ifndef PCDM_NT_RECORDS
 #define PCDM_NT_RECORDS 1
 #endif
@@ -70,6 +70,9 @@ constexpr int kHeader = 16;  // bytes of {x_i, 1/L_i} in front of each column
 
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef int v2i_t __attribute__((ext_vector_type(2)));
+typedef unsigned int v2u_t __attribute__((ext_vector_type(2)));
+typedef double v2d_t __attribute__((ext_vector_type(2)));
 
 template <typename T> __device__ __forceinline__ T ld_rec(const T *p)
 {
@@ -156,11 +159,11 @@ template <> struct Chunk4<float> {
 };
 
 template <> struct Chunk4<double> {
-    __device__ __forceinline__ static v4i_t bits16(const char *p) { return *reinterpret_cast<const v4i_t *>(p); }
+    __device__ __forceinline__ static v4i_t bits16(const char *p) { return ld_rec(reinterpret_cast<const v4i_t *>(p)); }
     __device__ __forceinline__ static void vals(const char *rows, int32_t dpad, int32_t e, double (&v)[4])
     {
-        const double2 b0 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e);
-        const double2 b1 = *reinterpret_cast<const double2 *>(rows + 4 * dpad + 8 * e + 16);
+        const v2d_t b0 = ld_rec(reinterpret_cast<const v2d_t *>(rows + 4 * dpad + 8 * e));
+        const v2d_t b1 = ld_rec(reinterpret_cast<const v2d_t *>(rows + 4 * dpad + 8 * e + 16));
         v[0] = b0.x; v[1] = b0.y; v[2] = b1.x; v[3] = b1.y;
     }
     __device__ __forceinline__ static void load(const char *rows, int32_t dpad, int32_t e, int (&rw)[4],
@@ -177,13 +180,13 @@ template <> struct Chunk4<double> {
 template <> struct Chunk4<bf16s> {
     __device__ __forceinline__ static v4i_t bits16(const char *p)
     {
-        const int2 a0 = *reinterpret_cast<const int2 *>(p);
-        const int2 a1 = *reinterpret_cast<const int2 *>(p + 8);
+        const v2i_t a0 = ld_rec(reinterpret_cast<const v2i_t *>(p));
+        const v2i_t a1 = ld_rec(reinterpret_cast<const v2i_t *>(p + 8));
         return v4i_t{a0.x, a0.y, a1.x, a1.y};
     }
     __device__ __forceinline__ static void vals(const char *rows, int32_t dpad, int32_t e, float (&v)[4])
     {
-        const uint2 b = *reinterpret_cast<const uint2 *>(rows + 4 * dpad + 2 * e);
+        const v2u_t b = ld_rec(reinterpret_cast<const v2u_t *>(rows + 4 * dpad + 2 * e));
         v[0] = __uint_as_float(b.x << 16);
         v[1] = __uint_as_float(b.x & 0xFFFF0000u);
         v[2] = __uint_as_float(b.y << 16);
