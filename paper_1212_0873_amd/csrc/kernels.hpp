@@ -504,8 +504,9 @@ __device__ __forceinline__ void gather_tile(char *__restrict__ seg, const Layout
         id_slot[slot] = (int32_t)i;
         delta_slot[slot] = (T)d;
         if (d != 0.0) {
-            *reinterpret_cast<double *>(seg + off) = xn;
-            xm[i] = xn;
+            // streaming stores: neither line is read again in this step
+            __builtin_nontemporal_store(xn, reinterpret_cast<double *>(seg + off));
+            __builtin_nontemporal_store(xn, xm + i);
             ++nz;
         }
     }
@@ -711,8 +712,9 @@ __device__ __forceinline__ void gather_slot_narrow(char *__restrict__ seg, const
         id_slot[slot] = (int32_t)i;
         delta_slot[slot] = (T)d;
         if (d != 0.0) {
-            *reinterpret_cast<double *>(seg + off) = xn;
-            xm[i] = xn;
+            // streaming stores: neither line is read again in this step
+            __builtin_nontemporal_store(xn, reinterpret_cast<double *>(seg + off));
+            __builtin_nontemporal_store(xn, xm + i);
             ++nz;
         }
     }
