@@ -447,7 +447,11 @@ int pcdm_batch_create(int count, const pcdm_csc *A, const double *const *b, cons
 int pcdm_batch_step(pcdm_batch *B, int64_t nsteps, void *stream);
 
 /* F_j and (if gap != NULL) the duality gap of every problem, float64
- * (arrays of `count`).  Synchronous. */
+ * (arrays of `count`).  Only the problems that stepped since their last
+ * evaluation are evaluated again (refresh of r = A x - b in float64, then
+ * the sums and ||A_j^T r_j||_inf); the others return the values of that
+ * evaluation, which still hold since neither x_j nor b_j changed.
+ * Synchronous. */
 int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream);
 
 /* active[j] = 0 holds problem j still (retired), 1 resumes it.  Synchronises the device. */

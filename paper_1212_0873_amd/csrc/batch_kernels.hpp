@@ -21,8 +21,6 @@ struct BatchInst {
     int64_t col_base;      // element offset into the x mirror
     int64_t slot_base;     // element offset into id_slot / delta_slot
     int64_t step_tile0;    // first step tile of this problem
-    int64_t col_tile0;     // first column tile
-    int64_t row_tile0;     // first row tile
     int64_t m, n, tau, spe;  // spe = steps per epoch = refresh period
     uint64_t seed, k;
     double inv_beta, lam;
@@ -78,46 +76,155 @@ k_batch_scatter(const char *__restrict__ seg, BatchInst *__restrict__ desc, cons
     }
 }
 
-// Problems whose float64 refresh is due after this step (k_j a multiple of
-// the epoch length), or every problem when `all` is set (objective).
-__device__ __forceinline__ bool batch_due(const BatchInst &d, int act, int all)
+// The problems a refresh or objective pass covers: those whose float64
+// refresh is due after this step (k_j a multiple of the epoch length), or,
+// with `sel` given, those with sel[j] != 0.  k_batch_list writes them once
+// per pass as a list with prefix sums of their column and row tiles; the
+// pass kernels then map a flat tile index onto (problem, tile) by a binary
+// search of the prefix sums held in LDS, so a step in which few problems are
+// due touches only their rows and columns.
+struct BatchList {
+    int32_t *n;       // [1] number of listed problems
+    int32_t *ids;     // [count]
+    int64_t *colp;    // [count + 1] prefix sums of ceil(n_j / 64)
+    int64_t *rowp;    // [count + 1] prefix sums of ceil(m_j / 64)
+};
+
+// One block.  Chunks of kBlock problems: flags and tile counts, a block
+// scan, then the selected problems are appended in order.
+__global__ void __launch_bounds__(kBlock)
+k_batch_list(const BatchInst *__restrict__ desc, const int32_t *__restrict__ active, int count,
+             const int32_t *__restrict__ sel, BatchList out)
 {
-    return all || (act && d.spe > 0 && d.k % (uint64_t)d.spe == 0);
+    __shared__ int32_t s_f[kBlock];
+    __shared__ int64_t s_c[kBlock], s_r[kBlock];
+    __shared__ int32_t s_base;
+    __shared__ int64_t s_cb, s_rb;
+    if (threadIdx.x == 0) {
+        s_base = 0;
+        s_cb = 0;
+        s_rb = 0;
+    }
+    __syncthreads();
+    for (int j0 = 0; j0 < count; j0 += kBlock) {
+        const int j = j0 + (int)threadIdx.x;
+        int32_t f = 0;
+        int64_t c = 0, r = 0;
+        if (j < count) {
+            const BatchInst &d = desc[j];
+            f = sel ? (sel[j] != 0) : (active[j] && d.spe > 0 && d.k % (uint64_t)d.spe == 0);
+            if (f) {
+                c = (d.n + 63) / 64;
+                r = (d.m + 63) / 64;
+            }
+        }
+        s_f[threadIdx.x] = f;
+        s_c[threadIdx.x] = c;
+        s_r[threadIdx.x] = r;
+        __syncthreads();
+        // inclusive scans (Hillis-Steele)
+        for (int o = 1; o < kBlock; o <<= 1) {
+            const int32_t fa = threadIdx.x >= (unsigned)o ? s_f[threadIdx.x - o] : 0;
+            const int64_t ca = threadIdx.x >= (unsigned)o ? s_c[threadIdx.x - o] : 0;
+            const int64_t ra = threadIdx.x >= (unsigned)o ? s_r[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_f[threadIdx.x] += fa;
+            s_c[threadIdx.x] += ca;
+            s_r[threadIdx.x] += ra;
+            __syncthreads();
+        }
+        if (f) {
+            const int q = s_base + s_f[threadIdx.x] - 1;
+            out.ids[q] = j;
+            out.colp[q] = s_cb + s_c[threadIdx.x] - c;
+            out.rowp[q] = s_rb + s_r[threadIdx.x] - r;
+        }
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) {
+            s_base += s_f[threadIdx.x];
+            s_cb += s_c[threadIdx.x];
+            s_rb += s_r[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out.n[0] = s_base;
+        out.colp[s_base] = s_cb;
+        out.rowp[s_base] = s_rb;
+    }
 }
 
-// r64 = -b over the row tiles of due problems.
-__global__ void __launch_bounds__(kBlock)
-k_batch_neg_b(const BatchInst *__restrict__ desc, const int32_t *__restrict__ active,
-              const int32_t *__restrict__ tile_inst, int64_t ntiles, const double *__restrict__ b,
-              double *__restrict__ r64, int all)
+// Loads the list's count and one prefix array into LDS (kMaxListLds entries
+// at most; longer lists are searched in global memory).
+constexpr int kMaxListLds = 1024;
+
+struct ListView {
+    int n;
+    const int64_t *p;  // LDS copy or global prefix sums [n + 1]
+    const int32_t *ids;
+    __device__ __forceinline__ int64_t total() const { return p[n]; }
+    // index q with p[q] <= t < p[q + 1]
+    __device__ __forceinline__ int find(int64_t t) const
+    {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (p[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return lo;
+    }
+};
+
+__device__ __forceinline__ ListView load_list(const BatchList &L, const int64_t *pref, int64_t *lds)
 {
+    ListView v;
+    v.n = L.n[0];
+    v.ids = L.ids;
+    if (v.n + 1 <= kMaxListLds) {
+        for (int q = threadIdx.x; q <= v.n; q += kBlock)
+            lds[q] = pref[q];
+        __syncthreads();
+        v.p = lds;
+    } else {
+        v.p = pref;
+    }
+    return v;
+}
+
+// r64 = -b over the rows of the listed problems.
+__global__ void __launch_bounds__(kBlock)
+k_batch_neg_b(const BatchInst *__restrict__ desc, BatchList L, const double *__restrict__ b,
+              double *__restrict__ r64)
+{
+    __shared__ int64_t lds[kMaxListLds];
+    const ListView v = load_list(L, L.rowp, lds);
     const int lane = threadIdx.x & 63;
-    for (int64_t t = wave_global_id(); t < ntiles; t += wave_count()) {
-        const int j = tile_inst[t];
-        const BatchInst &d = desc[j];
-        if (!batch_due(d, active[j], all))
-            continue;
-        const int64_t row = (t - d.row_tile0) * 64 + lane;
+    for (int64_t t = wave_global_id(); t < v.total(); t += wave_count()) {
+        const int q = v.find(t);
+        const BatchInst &d = desc[v.ids[q]];
+        const int64_t row = (t - v.p[q]) * 64 + lane;
         if (row < d.m)
             r64[d.row_base + row] = -b[d.row_base + row];
     }
 }
 
-// r64 += x_i a_i over the column tiles of due problems (float64 atomics).
+// r64 += x_i a_i over the columns of the listed problems (float64 atomics).
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
-k_batch_refresh_cols(const char *__restrict__ seg, const BatchInst *__restrict__ desc,
-                     const int32_t *__restrict__ active, const int32_t *__restrict__ tile_inst, int64_t ntiles,
-                     const double *__restrict__ xm, double *__restrict__ r64, int all)
+k_batch_refresh_cols(const char *__restrict__ seg, const BatchInst *__restrict__ desc, BatchList L,
+                     const double *__restrict__ xm, double *__restrict__ r64)
 {
     using T = typename ValT<V>::T;
+    __shared__ int64_t lds[kMaxListLds];
+    const ListView v = load_list(L, L.colp, lds);
     const TileLanes<G> tl;
-    for (int64_t t = wave_global_id(); t < ntiles; t += wave_count()) {
-        const int j = tile_inst[t];
-        const BatchInst &d = desc[j];
-        if (!batch_due(d, active[j], all))
-            continue;
-        const int64_t col = (t - d.col_tile0) * 64 + tl.lane;
+    for (int64_t t = wave_global_id(); t < v.total(); t += wave_count()) {
+        const int q = v.find(t);
+        const BatchInst &d = desc[v.ids[q]];
+        const int64_t col = (t - v.p[q]) * 64 + tl.lane;
         const double xi = col < d.n ? xm[d.col_base + col] : 0.0;
         const bool live = xi != 0.0;
         if (!__any(live))
@@ -134,41 +241,43 @@ k_batch_refresh_cols(const char *__restrict__ seg, const BatchInst *__restrict__
     }
 }
 
-// r = (T) r64 over the row tiles of due problems.
+// r = (T) r64 over the rows of the listed problems.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_batch_narrow(const BatchInst *__restrict__ desc, const int32_t *__restrict__ active,
-               const int32_t *__restrict__ tile_inst, int64_t ntiles, const double *__restrict__ r64,
-               T *__restrict__ r)
+k_batch_narrow(const BatchInst *__restrict__ desc, BatchList L, const double *__restrict__ r64, T *__restrict__ r)
 {
+    __shared__ int64_t lds[kMaxListLds];
+    const ListView v = load_list(L, L.rowp, lds);
     const int lane = threadIdx.x & 63;
-    for (int64_t t = wave_global_id(); t < ntiles; t += wave_count()) {
-        const int j = tile_inst[t];
-        const BatchInst &d = desc[j];
-        if (!batch_due(d, active[j], 0))
-            continue;
-        const int64_t row = (t - d.row_tile0) * 64 + lane;
+    for (int64_t t = wave_global_id(); t < v.total(); t += wave_count()) {
+        const int q = v.find(t);
+        const BatchInst &d = desc[v.ids[q]];
+        const int64_t row = (t - v.p[q]) * 64 + lane;
         if (row < d.m)
             r[d.row_base + row] = (T)r64[d.row_base + row];
     }
 }
 
-// Per-problem objective pieces: acc[4j+0] += ||r64||^2, acc[4j+1] += b.r64
-// (row tiles) and acc[4j+2] += ||x||_1 (column tiles, see k_batch_cols_obj).
+// Per-problem objective pieces of the listed problems: acc[4j+0] +=
+// ||r64||^2, acc[4j+1] += b.r64 (rows) and acc[4j+2] += ||x||_1 (columns, see
+// k_batch_col_obj).
 __global__ void __launch_bounds__(kBlock)
-k_batch_row_sums(const BatchInst *__restrict__ desc, const int32_t *__restrict__ tile_inst, int64_t ntiles,
-                 const double *__restrict__ b, const double *__restrict__ r64, double *__restrict__ acc)
+k_batch_row_sums(const BatchInst *__restrict__ desc, BatchList L, const double *__restrict__ b,
+                 const double *__restrict__ r64, double *__restrict__ acc)
 {
+    __shared__ int64_t lds[kMaxListLds];
+    const ListView v = load_list(L, L.rowp, lds);
     const int lane = threadIdx.x & 63;
-    for (int64_t t = wave_global_id(); t < ntiles; t += wave_count()) {
-        const int j = tile_inst[t];
+    for (int64_t t = wave_global_id(); t < v.total(); t += wave_count()) {
+        const int q = v.find(t);
+        const int j = v.ids[q];
         const BatchInst &d = desc[j];
-        const int64_t row = (t - d.row_tile0) * 64 + lane;
+        const int64_t row = (t - v.p[q]) * 64 + lane;
         double rr = 0.0, br = 0.0;
         if (row < d.m) {
-            const double v = r64[d.row_base + row];
-            rr = v * v;
-            br = b[d.row_base + row] * v;
+            const double x = r64[d.row_base + row];
+            rr = x * x;
+            br = b[d.row_base + row] * x;
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -182,20 +291,23 @@ k_batch_row_sums(const BatchInst *__restrict__ desc, const int32_t *__restrict__
     }
 }
 
-// acc[4j+2] += ||x_j||_1 and acc[4j+3] = max(|a_i^T r64|) over column tiles.
-// The max goes through the unsigned bit pattern (monotone for values >= 0).
+// acc[4j+2] += ||x_j||_1 and acc[4j+3] = max(|a_i^T r64|) over the columns
+// of the listed problems.  The max goes through the unsigned bit pattern
+// (monotone for values >= 0).
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
-k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc,
-                const int32_t *__restrict__ tile_inst, int64_t ntiles, const double *__restrict__ xm,
-                const double *__restrict__ r64, double *__restrict__ acc)
+k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc, BatchList L,
+                const double *__restrict__ xm, const double *__restrict__ r64, double *__restrict__ acc)
 {
     using T = typename ValT<V>::T;
+    __shared__ int64_t lds[kMaxListLds];
+    const ListView v = load_list(L, L.colp, lds);
     const TileLanes<G> tl;
-    for (int64_t t = wave_global_id(); t < ntiles; t += wave_count()) {
-        const int j = tile_inst[t];
+    for (int64_t t = wave_global_id(); t < v.total(); t += wave_count()) {
+        const int q = v.find(t);
+        const int j = v.ids[q];
         const BatchInst &d = desc[j];
-        const int64_t col = (t - d.col_tile0) * 64 + tl.lane;
+        const int64_t col = (t - v.p[q]) * 64 + tl.lane;
         int64_t off = 0;
         int32_t dp = 0;
         double ax = 0.0;
@@ -205,18 +317,18 @@ k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc
         }
         double a[G];
 #pragma unroll
-        for (int q = 0; q < G; ++q)
-            a[q] = 0.0;
+        for (int g = 0; g < G; ++g)
+            a[g] = 0.0;
         const double *rr = r64 + d.row_base;
-        tile_entries<V, G>(seg + d.rec_base, tl, off, dp, 0, [&](int q, int, int row, T val) {
-            a[q] += (double)val * rr[row];
+        tile_entries<V, G>(seg + d.rec_base, tl, off, dp, 0, [&](int g, int, int row, T val) {
+            a[g] += (double)val * rr[row];
         });
         double mine = 0.0;
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const double s = group_sum<G>(a[q]);
-            const double got = __shfl(s, tl.leader_of_mine(q));
-            if (tl.lane / TileLanes<G>::CPR == q)
+        for (int g = 0; g < G; ++g) {
+            const double sq = group_sum<G>(a[g]);
+            const double got = __shfl(sq, tl.leader_of_mine(g));
+            if (tl.lane / TileLanes<G>::CPR == g)
                 mine = got;
         }
         double gm = col < d.n ? fabs(mine) : 0.0;

@@ -21,9 +21,20 @@ struct pcdm_batch {
     void *r = nullptr, *delta_slot = nullptr;
     int32_t *id_slot = nullptr, *active = nullptr;
     BatchInst *desc = nullptr;
-    int32_t *step_tiles = nullptr, *col_tiles = nullptr, *row_tiles = nullptr;
-    int64_t n_step_tiles = 0, n_col_tiles = 0, n_row_tiles = 0;
+    int32_t *step_tiles = nullptr;
+    int64_t n_step_tiles = 0;
+    int64_t n_col_tiles = 0, n_row_tiles = 0;  // over all problems
     uint64_t *nz_part = nullptr;
+    BatchList list{nullptr, nullptr, nullptr, nullptr};  // problems of the current refresh / objective pass
+
+    // objective: problems evaluated by the next call (device copy of hsel),
+    // and the last values of each problem with the step count they hold for
+    // (a problem that has not stepped since keeps them)
+    int32_t *sel = nullptr;
+    std::vector<int32_t> hsel;
+    std::vector<double> cF, cG;
+    std::vector<int64_t> ck;
+    std::vector<char> cvalid;
 
     int lanes = 4, chunks = 1;
     int64_t graph_len = 32;  // steps per captured graph; 0 = no graph
@@ -52,7 +63,8 @@ void batch_free(pcdm_batch *B)
         return;
     batch_drop_graph(B);
     void *bufs[] = {B->seg, B->pc_all, B->x, B->r64, B->b, B->acc, B->r, B->delta_slot, B->id_slot, B->active,
-                    B->desc, B->step_tiles, B->col_tiles, B->row_tiles, B->nz_part};
+                    B->desc, B->step_tiles, B->nz_part, B->sel, B->list.n, B->list.ids, B->list.colp,
+                    B->list.rowp};
     for (void *q : bufs)
         if (q)
             (void)hipFree(q);
@@ -73,10 +85,11 @@ template <typename V> struct BatchOps {
         hipLaunchKernelGGL((k_batch_scatter<V, G>), dim3(gs), dim3(kBlock), 0, s, (const char *)B->seg, B->desc,
                            (const int32_t *)B->active, B->count, (const int32_t *)B->step_tiles, B->n_step_tiles,
                            (T *)B->r, (const int32_t *)B->id_slot, (const T *)B->delta_slot);
-        refresh(B, s, 0);
+        list(B, s, nullptr);
+        refresh(B, s);
         hipLaunchKernelGGL((k_batch_narrow<T>), dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)),
-                           dim3(kBlock), 0, s, (const BatchInst *)B->desc, (const int32_t *)B->active,
-                           (const int32_t *)B->row_tiles, B->n_row_tiles, (const double *)B->r64, (T *)B->r);
+                           dim3(kBlock), 0, s, (const BatchInst *)B->desc, B->list, (const double *)B->r64,
+                           (T *)B->r);
     }
 
     static int step_once(pcdm_batch *B, hipStream_t s)
@@ -100,37 +113,45 @@ template <typename V> struct BatchOps {
         return PCDM_OK;
     }
 
-    // r64 = A x - b for due problems (every problem when all = 1).
-    static void refresh(pcdm_batch *B, hipStream_t s, int all)
+    // B->list = the problems due after this step, or (sel given) those with
+    // sel[j] != 0.
+    static void list(pcdm_batch *B, hipStream_t s, const int32_t *sel)
     {
-        hipLaunchKernelGGL(k_batch_neg_b, dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)), dim3(kBlock), 0,
-                           s, (const BatchInst *)B->desc, (const int32_t *)B->active, (const int32_t *)B->row_tiles,
-                           B->n_row_tiles, (const double *)B->b, B->r64, all);
-        hipLaunchKernelGGL((k_batch_refresh_cols<V, 8>), dim3(grid_for(B->n_col_tiles * 64, kBlock, B->nblk_max)),
-                           dim3(kBlock), 0, s, (const char *)B->seg, (const BatchInst *)B->desc,
-                           (const int32_t *)B->active, (const int32_t *)B->col_tiles, B->n_col_tiles,
-                           (const double *)B->x, B->r64, all);
+        hipLaunchKernelGGL(k_batch_list, dim3(1), dim3(kBlock), 0, s, (const BatchInst *)B->desc,
+                           (const int32_t *)B->active, B->count, sel, B->list);
     }
 
+    // r64 = A x - b for the listed problems.
+    static void refresh(pcdm_batch *B, hipStream_t s)
+    {
+        hipLaunchKernelGGL(k_batch_neg_b, dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)), dim3(kBlock), 0,
+                           s, (const BatchInst *)B->desc, B->list, (const double *)B->b, B->r64);
+        hipLaunchKernelGGL((k_batch_refresh_cols<V, 8>), dim3(grid_for(B->n_col_tiles * 64, kBlock, B->nblk_max)),
+                           dim3(kBlock), 0, s, (const char *)B->seg, (const BatchInst *)B->desc, B->list,
+                           (const double *)B->x, B->r64);
+    }
+
+    // acc[4j..4j+3] for the problems with B->sel[j] != 0 (others zero).
     static void objective(pcdm_batch *B, hipStream_t s)
     {
-        refresh(B, s, 1);
+        list(B, s, B->sel);
+        refresh(B, s);
         hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, s, B->acc, 0.0, (int64_t)4 * B->count);
-        hipLaunchKernelGGL(k_batch_row_sums, dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)), dim3(kBlock),
-                           0, s, (const BatchInst *)B->desc, (const int32_t *)B->row_tiles, B->n_row_tiles,
-                           (const double *)B->b, (const double *)B->r64, B->acc);
-        hipLaunchKernelGGL((k_batch_col_obj<V, 8>), dim3(grid_for(B->n_col_tiles * 64, kBlock, B->nblk_max)),
-                           dim3(kBlock), 0, s, (const char *)B->seg, (const BatchInst *)B->desc,
-                           (const int32_t *)B->col_tiles, B->n_col_tiles, (const double *)B->x,
+        hipLaunchKernelGGL(k_batch_row_sums, dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)),
+                           dim3(kBlock), 0, s, (const BatchInst *)B->desc, B->list, (const double *)B->b,
                            (const double *)B->r64, B->acc);
+        hipLaunchKernelGGL((k_batch_col_obj<V, 8>), dim3(grid_for(B->n_col_tiles * 64, kBlock, B->nblk_max)),
+                           dim3(kBlock), 0, s, (const char *)B->seg, (const BatchInst *)B->desc, B->list,
+                           (const double *)B->x, (const double *)B->r64, B->acc);
     }
 
     static void narrow_all(pcdm_batch *B, hipStream_t s)
     {
         // at k = 0 every active problem is due
+        list(B, s, nullptr);
         hipLaunchKernelGGL((k_batch_narrow<T>), dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)),
-                           dim3(kBlock), 0, s, (const BatchInst *)B->desc, (const int32_t *)B->active,
-                           (const int32_t *)B->row_tiles, B->n_row_tiles, (const double *)B->r64, (T *)B->r);
+                           dim3(kBlock), 0, s, (const BatchInst *)B->desc, B->list, (const double *)B->r64,
+                           (T *)B->r);
     }
 
     static void pack(pcdm_batch *B, const int64_t *col_ptr, const int32_t *rows, const void *vals, int j,
@@ -315,8 +336,6 @@ int batch_create_impl(int count, const pcdm_csc *A, const double *const *b, cons
         d.col_base = col_base;
         d.slot_base = slot_base;
         d.step_tile0 = step_t;
-        d.col_tile0 = col_t;
-        d.row_tile0 = row_t;
         d.m = a.m;
         d.n = a.n;
         d.tau = tau[j];
@@ -351,19 +370,24 @@ int batch_create_impl(int count, const pcdm_csc *A, const double *const *b, cons
     HIP_TRY(hipMalloc(&B->nz_part, 8 * (size_t)B->nblk_max));
     HIP_TRY(hipMemset(B->nz_part, 0, 8 * (size_t)B->nblk_max));
     {
-        std::vector<int32_t> st(step_t), ct(col_t), rt(row_t);
+        std::vector<int32_t> st(step_t);
         for (int j = 0; j < count; ++j) {
             const BatchInst &d = B->hdesc[j];
             for (int64_t t = 0; t < ceil_div(d.tau, 64); ++t) st[d.step_tile0 + t] = j;
-            for (int64_t t = 0; t < ceil_div(d.n, 64); ++t) ct[d.col_tile0 + t] = j;
-            for (int64_t t = 0; t < ceil_div(d.m, 64); ++t) rt[d.row_tile0 + t] = j;
         }
+        HIP_TRY(hipMalloc(&B->list.n, 4));
+        HIP_TRY(hipMalloc(&B->list.ids, 4 * (size_t)count));
+        HIP_TRY(hipMalloc(&B->list.colp, 8 * ((size_t)count + 1)));
+        HIP_TRY(hipMalloc(&B->list.rowp, 8 * ((size_t)count + 1)));
         HIP_TRY(hipMalloc(&B->step_tiles, 4 * (size_t)step_t));
-        HIP_TRY(hipMalloc(&B->col_tiles, 4 * (size_t)col_t));
-        HIP_TRY(hipMalloc(&B->row_tiles, 4 * (size_t)row_t));
         HIP_TRY(hipMemcpy(B->step_tiles, st.data(), 4 * (size_t)step_t, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(B->col_tiles, ct.data(), 4 * (size_t)col_t, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(B->row_tiles, rt.data(), 4 * (size_t)row_t, hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc(&B->sel, 4 * (size_t)count));
+        B->hsel.assign(count, 1);
+        HIP_TRY(hipMemcpy(B->sel, B->hsel.data(), 4 * (size_t)count, hipMemcpyHostToDevice));
+        B->cF.assign(count, 0.0);
+        B->cG.assign(count, 0.0);
+        B->ck.assign(count, -1);
+        B->cvalid.assign(count, 0);
     }
 
     // pass 2: pack every problem, omega_j, b_j
@@ -488,22 +512,38 @@ int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream)
     if (!B || !F)
         return fail(PCDM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    PCDM_TRY(batch_dispatch(B->dtype, [&](auto ops) {
-        decltype(ops)::objective(B, s);
-        return PCDM_OK;
-    }));
-    PCDM_TRY(check_launch("pcdm_batch_objective"));
-    std::vector<double> acc(4 * (size_t)B->count);
-    HIP_TRY(hipMemcpyAsync(acc.data(), B->acc, 32 * (size_t)B->count, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // Evaluate the problems that stepped since their last evaluation (or never
+    // had one); the others have not changed and keep their values.
+    bool any = false;
     for (int j = 0; j < B->count; ++j) {
-        const double rr = acc[4 * j], br = acc[4 * j + 1], l1 = acc[4 * j + 2], gm = acc[4 * j + 3];
-        const double lam = B->lambda[j];
-        F[j] = 0.5 * rr + lam * l1;
-        if (gap) {
+        B->hsel[j] = (!B->cvalid[j] || B->ck[j] != B->k_host[j]) ? 1 : 0;
+        any = any || B->hsel[j];
+    }
+    std::vector<double> acc(4 * (size_t)B->count, 0.0);
+    if (any) {
+        HIP_TRY(hipMemcpyAsync(B->sel, B->hsel.data(), 4 * (size_t)B->count, hipMemcpyHostToDevice, s));
+        PCDM_TRY(batch_dispatch(B->dtype, [&](auto ops) {
+            decltype(ops)::objective(B, s);
+            return PCDM_OK;
+        }));
+        PCDM_TRY(check_launch("pcdm_batch_objective"));
+        HIP_TRY(hipMemcpyAsync(acc.data(), B->acc, 32 * (size_t)B->count, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    for (int j = 0; j < B->count; ++j) {
+        if (B->hsel[j]) {
+            const double rr = acc[4 * j], br = acc[4 * j + 1], l1 = acc[4 * j + 2], gm = acc[4 * j + 3];
+            const double lam = B->lambda[j];
+            const double Fj = 0.5 * rr + lam * l1;
             const double sc = gm > lam ? lam / gm : 1.0;
-            gap[j] = F[j] - (-0.5 * sc * sc * rr - sc * br);
+            B->cF[j] = Fj;
+            B->cG[j] = Fj - (-0.5 * sc * sc * rr - sc * br);
+            B->ck[j] = B->k_host[j];
+            B->cvalid[j] = 1;
         }
+        F[j] = B->cF[j];
+        if (gap)
+            gap[j] = B->cG[j];
     }
     return PCDM_OK;
 }
