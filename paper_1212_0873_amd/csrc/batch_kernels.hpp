@@ -53,29 +53,6 @@ k_batch_gather(char *__restrict__ seg, const BatchInst *__restrict__ desc, const
         nz_part[blockIdx.x] += tot;
 }
 
-// Phase 2 for every active problem; block 0 advances each active k_j.
-template <typename V, int G>
-__global__ void __launch_bounds__(kBlock)
-k_batch_scatter(const char *__restrict__ seg, BatchInst *__restrict__ desc, const int32_t *__restrict__ active,
-                int count, const int32_t *__restrict__ tile_inst, int64_t ntiles,
-                typename ValT<V>::T *__restrict__ r, const int32_t *__restrict__ id_slot,
-                const typename ValT<V>::T *__restrict__ delta_slot)
-{
-    if (blockIdx.x == 0)
-        for (int j = threadIdx.x; j < count; j += kBlock)
-            if (active[j])
-                desc[j].k += 1;  // no block of this kernel reads k
-    const TileLanes<G> tl;
-    for (int64_t t = wave_global_id(); t < ntiles; t += wave_count()) {
-        const int j = tile_inst[t];
-        if (!active[j])
-            continue;
-        const BatchInst &d = desc[j];
-        scatter_tile<V, G>(seg + d.rec_base, d.lay, r + d.row_base, id_slot + d.slot_base,
-                           delta_slot + d.slot_base, tl, (t - d.step_tile0) * 64, d.tau);
-    }
-}
-
 // The problems a refresh or objective pass covers: those whose float64
 // refresh is due after this step (k_j a multiple of the epoch length), or,
 // with `sel` given, those with sel[j] != 0.  k_batch_list writes them once
@@ -91,10 +68,10 @@ struct BatchList {
 };
 
 // One block.  Chunks of kBlock problems: flags and tile counts, a block
-// scan, then the selected problems are appended in order.
-__global__ void __launch_bounds__(kBlock)
-k_batch_list(const BatchInst *__restrict__ desc, const int32_t *__restrict__ active, int count,
-             const int32_t *__restrict__ sel, BatchList out)
+// scan, then the selected problems are appended in order.  Every thread of
+// the block must call it (it synchronises the block).
+__device__ void batch_list_body(const BatchInst *__restrict__ desc, const int32_t *__restrict__ active, int count,
+                                const int32_t *__restrict__ sel, const BatchList &out)
 {
     __shared__ int32_t s_f[kBlock];
     __shared__ int64_t s_c[kBlock], s_r[kBlock];
@@ -151,6 +128,41 @@ k_batch_list(const BatchInst *__restrict__ desc, const int32_t *__restrict__ act
         out.n[0] = s_base;
         out.colp[s_base] = s_cb;
         out.rowp[s_base] = s_rb;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_batch_list(const BatchInst *__restrict__ desc, const int32_t *__restrict__ active, int count,
+             const int32_t *__restrict__ sel, BatchList out)
+{
+    batch_list_body(desc, active, count, sel, out);
+}
+
+// Phase 2 for every active problem; block 0 also advances k_j of the active
+// problems and then lists the problems whose refresh is due after this step
+// (the list the refresh kernels that follow read).
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_batch_scatter(const char *__restrict__ seg, BatchInst *__restrict__ desc, const int32_t *__restrict__ active,
+                int count, const int32_t *__restrict__ tile_inst, int64_t ntiles,
+                typename ValT<V>::T *__restrict__ r, const int32_t *__restrict__ id_slot,
+                const typename ValT<V>::T *__restrict__ delta_slot, BatchList due)
+{
+    if (blockIdx.x == 0) {
+        for (int j = threadIdx.x; j < count; j += kBlock)
+            if (active[j])
+                desc[j].k += 1;  // other blocks of this kernel do not read k
+        __syncthreads();
+        batch_list_body(desc, active, count, nullptr, due);
+    }
+    const TileLanes<G> tl;
+    for (int64_t t = wave_global_id(); t < ntiles; t += wave_count()) {
+        const int j = tile_inst[t];
+        if (!active[j])
+            continue;
+        const BatchInst &d = desc[j];
+        scatter_tile<V, G>(seg + d.rec_base, d.lay, r + d.row_base, id_slot + d.slot_base,
+                           delta_slot + d.slot_base, tl, (t - d.step_tile0) * 64, d.tau);
     }
 }
 

@@ -84,9 +84,8 @@ template <typename V> struct BatchOps {
                            B->n_step_tiles, (const T *)B->r, B->x, B->id_slot, (T *)B->delta_slot, B->nz_part);
         hipLaunchKernelGGL((k_batch_scatter<V, G>), dim3(gs), dim3(kBlock), 0, s, (const char *)B->seg, B->desc,
                            (const int32_t *)B->active, B->count, (const int32_t *)B->step_tiles, B->n_step_tiles,
-                           (T *)B->r, (const int32_t *)B->id_slot, (const T *)B->delta_slot);
-        list(B, s, nullptr);
-        refresh(B, s);
+                           (T *)B->r, (const int32_t *)B->id_slot, (const T *)B->delta_slot, B->list);
+        refresh(B, s);  // the scatter listed the due problems
         hipLaunchKernelGGL((k_batch_narrow<T>), dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)),
                            dim3(kBlock), 0, s, (const BatchInst *)B->desc, B->list, (const double *)B->r64,
                            (T *)B->r);
