@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from tests import pins
-from workloads import (csc_to_dense, dense_to_csc, orthonormal_block_hadamard, planted_lasso,
+from workloads import (csc_to_dense, dense_to_csc, make_config, orthonormal_block_hadamard, planted_lasso,
                        random_csc, separable_matrix, tightness_matrix)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -373,3 +373,24 @@ def test_sampler_inclusion_and_pair_probabilities():
     zz = (off - pij) / math.sqrt(pij * (1 - pij) / K)
     assert np.max(np.abs(zz)) < 5.0
     assert abs(off.mean() - pij) < 3 * math.sqrt(pij / (K * n * n))
+
+
+def test_checkpoint_resume_follows_the_same_trajectory():
+    """Fault/resume: the state of a run is (x, k) with the seed; a fresh run
+    started from a checkpoint (x_k, k) draws the same S_k, S_k+1, ... and
+    ends where the uninterrupted run ends (up to the rounding of r, which the
+    resumed run recomputes from x)."""
+    inst = make_config("small_2000x1000", dtype="f64")
+    full = oracle.Solver(inst.A, inst.b, inst.lam, tau=8, seed=3)
+    full.step(300)
+    x_mid = full.x.copy()
+    full.step(200)
+    resumed = oracle.Solver(inst.A, inst.b, inst.lam, tau=8, seed=3, x0=x_mid)
+    resumed.k = 300
+    resumed.step(200)
+    np.testing.assert_allclose(resumed.x, full.x, rtol=0, atol=1e-12)
+    assert resumed.objective() == pytest.approx(full.objective(), rel=1e-13)
+    # a wrong step counter draws other sets and leaves the trajectory
+    wrong = oracle.Solver(inst.A, inst.b, inst.lam, tau=8, seed=3, x0=x_mid)
+    wrong.step(200)
+    assert np.max(np.abs(wrong.x - full.x)) > 1e-6
