@@ -111,6 +111,8 @@ typedef struct pcdm_info {
     double l2, linear, lower, upper;
     int64_t async_picks;     /* picks made by pcdm_step_async so far              */
     int64_t async_processors;/* processors (lane groups) of its last launch       */
+    int64_t max_incremental; /* ||A^T r||_inf evaluations that took route 3       */
+    int64_t max_candidates;  /* columns summed exactly by route 3's last attempt  */
 } pcdm_info;
 
 /*
@@ -131,8 +133,8 @@ typedef struct pcdm_info {
  * bytes; with equal column lengths every record is padded to 64 bytes),
  * 8 (n + 1) bytes of column pointers, x (8 n), r (m * sizeof(working type)),
  * r64 and b (8 m each), per-slot results (tau * (4 + sizeof(working type)))
- * and, for float32 / bf16 values, 4 (m + n) bytes for the two-pass
- * ||A^T r||_inf (option "max_passes").
+ * and, for float32 / bf16 values, 12 m + 8 n bytes for the two-pass and
+ * incremental ||A^T r||_inf (option "max_passes").
  */
 int pcdm_create(const pcdm_csc *A, const double *b, double lambda, int64_t tau,
                 uint64_t seed, pcdm_problem **out);
@@ -266,12 +268,19 @@ const char *pcdm_last_error(void);
  *                      step kernels changes (options, masks, sampling);
  *   "max_passes"       how ||A^T r||_inf (duality gap, ||A^T b||_inf; for
  *                      blocks max_i ||A_i^T r||_2) is
- *                      found for float32 / bf16 values: 2 (default) = a pass
+ *                      found for float32 / bf16 values: 2 = a pass
  *                      over fl32(r) giving every column (block) a rigorous
  *                      bound, then the exact float64 sums for the columns
  *                      (blocks) whose bound reaches the largest lower bound;
- *                      1 = the exact sums everywhere.  Both give the same number;
- *                      float64 values always take one pass;
+ *                      1 = the exact sums everywhere; 3 (default) = as 2, keeping r and
+ *                      the bounds of the last evaluation: the next one moves
+ *                      each column's bound by ||a_i||_2 times a rigorous bound
+ *                      on the change of r (Cauchy-Schwarz) and, when at most
+ *                      n/8 columns can still reach the maximum, sums only
+ *                      those exactly (one pass over r and the candidate
+ *                      records; the host reads the candidate count).  All
+ *                      three give the same number; float64 values always
+ *                      take one pass, blocks take 2 for 3;
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
  *                      settings of pcdm_grad_backward's solve (see there);

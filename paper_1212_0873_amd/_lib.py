@@ -44,7 +44,9 @@ class pcdm_info(ctypes.Structure):
                 ("reserved1", ctypes.c_int32),
                 ("loss_scale", ctypes.c_double), ("l2", ctypes.c_double), ("linear", ctypes.c_double),
                 ("lower", ctypes.c_double), ("upper", ctypes.c_double), ("async_picks", ctypes.c_int64),
-                ("async_processors", ctypes.c_int64)]
+                ("async_processors", ctypes.c_int64),
+                ("max_incremental", ctypes.c_int64),
+                ("max_candidates", ctypes.c_int64)]
 
 
 class pcdm_model(ctypes.Structure):

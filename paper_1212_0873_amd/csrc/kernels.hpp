@@ -1295,6 +1295,167 @@ k_atr_exact(const char *__restrict__ seg, Layout lay, const double *__restrict__
         part[blockIdx.x] = best;
 }
 
+// Incremental route between two evaluations of ||A^T r||_inf (float32 /
+// bf16 values).  Kept from the last evaluation: r_old (the r64 it used),
+// ub_i >= |a_i^T r_old| as the exact pass sums it, for every column, and its
+// result M_old.  For the new r64, Cauchy-Schwarz gives
+//     |a_i^T r_new| <= |a_i^T r_old| + ||a_i|| ||r_new - r_old||,
+// so with D = ||r_new - r_old|| + 2 gamma max(||r_old||, ||r_new||) (gamma =
+// (d_max + 2) 2^-52 covers the rounding of both exact sums) every column's
+// exact sum is at most ub_i + ||a_i|| D, and the new maximum is at least
+// M_old - max_i ||a_i|| D (the old maximiser moved by at most that).  Only
+// the columns whose bound reaches that lower bound are summed exactly; the
+// bounds of the others grow by ||a_i|| D.  The result is the single pass's.
+//
+// inc[0] = M_old, inc[1..3] = sum (r - r_old)^2, sum r^2, sum r_old^2,
+// inc[4] = D, inc[5] = the lower bound.
+
+// part[3 blk + {0, 1, 2}] = partial sums of (r - r_old)^2, r^2, r_old^2.
+__global__ void __launch_bounds__(kBlock)
+k_inc_sums(const double *__restrict__ r, const double *__restrict__ ro, int64_t m, double *__restrict__ part)
+{
+    __shared__ double lds[kBlock];
+    double dd = 0.0, rr = 0.0, oo = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m; j += (int64_t)gridDim.x * kBlock) {
+        const double a = r[j], o = ro[j];
+        dd += (a - o) * (a - o);
+        rr += a * a;
+        oo += o * o;
+    }
+    dd = block_sum_f64(dd, lds);
+    rr = block_sum_f64(rr, lds);
+    oo = block_sum_f64(oo, lds);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = dd;
+        part[3 * blockIdx.x + 1] = rr;
+        part[3 * blockIdx.x + 2] = oo;
+    }
+}
+
+// One thread: D and the lower bound from the sums (each sum of m terms is
+// within (m + 4) 2^-52 of its exact value, relative).
+__global__ void k_inc_prepare(double *__restrict__ inc, double nrm_max, double gam, double m)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    const double up = 1.0 + (m + 4.0) * 0x1p-52;
+    const double dlt = sqrt(inc[1] * up) * (1.0 + 0x1p-50);
+    const double rmax = sqrt(fmax(inc[2], inc[3]) * up) * (1.0 + 0x1p-50);
+    const double D = (dlt + 2.0 * gam * rmax) * (1.0 + 0x1p-40);
+    inc[4] = D;
+    inc[5] = (inc[0] - nrm_max * D) * (1.0 - 0x1p-40) - 0x1p-1000;
+}
+
+__device__ __forceinline__ float round_up_f32(double v)
+{
+    if (!(v < 3.0e38))
+        return __builtin_inff();
+    float u = (float)v;
+    if ((double)u < v)
+        u = __int_as_float(__float_as_int(u) + 1);  // next float up (v >= 0)
+    return u;
+}
+
+// *cnt += the number of columns whose bound reaches the lower bound.
+__global__ void __launch_bounds__(kBlock)
+k_inc_count(const float *__restrict__ ub, const float *__restrict__ nrm, int64_t n, const double *__restrict__ inc,
+            unsigned long long *__restrict__ cnt)
+{
+    __shared__ uint64_t s_red[kBlock / 64];
+    const double D = inc[4], lo = inc[5];
+    uint64_t c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        c += !((double)ub[i] * (1.0 + 0x1p-40) + (double)nrm[i] * D < lo);
+    c = block_sum_u64(c, s_red);
+    if (threadIdx.x == 0 && c)
+        atomicAdd(cnt, (unsigned long long)c);
+}
+
+// The candidates' exact sums (as k_atr_absmax forms them) and their maximum;
+// ub_i becomes the exact value (rounded up) for a candidate and
+// ub_i + ||a_i|| D (rounded up) for the others.
+template <typename V, int G>
+__global__ void __launch_bounds__(kBlock)
+k_atr_inc(const char *__restrict__ seg, Layout lay, const double *__restrict__ r64, int64_t n,
+          float *__restrict__ ub, const float *__restrict__ nrm, const double *__restrict__ inc,
+          double *__restrict__ part)
+{
+    using T = typename ValT<V>::T;
+    __shared__ double lds[kBlock];
+    const TileLanes<G> tl;
+    const double D = inc[4], lo = inc[5];
+    double best = 0.0;
+    for (int64_t base = wave_global_id() * 64; base < n; base += wave_count() * 64) {
+        const int64_t col = base + tl.lane;
+        double bnd = 0.0;
+        bool cand = false;
+        if (col < n) {
+            bnd = (double)ub[col] * (1.0 + 0x1p-40) + (double)nrm[col] * D;
+            cand = !(bnd < lo);
+        }
+        if (__any(cand)) {
+            int64_t off = 0;
+            int32_t dp = 0;
+            if (cand)
+                locate<V>(lay, col, off, dp);
+            double acc[G];
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+                acc[q] = 0.0;
+            tile_entries<V, G>(seg, tl, off, dp, 0, [&](int q, int, int row, T val) {
+                acc[q] += (double)val * r64[row];
+            });
+            double mine = 0.0;
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const double s = group_sum<G>(acc[q]);
+                const double got = __shfl(s, tl.leader_of_mine(q));
+                if (tl.lane / TileLanes<G>::CPR == q)
+                    mine = got;
+            }
+            if (cand) {
+                best = fmax(best, fabs(mine));
+                bnd = fabs(mine);
+            }
+        }
+        if (col < n)
+            ub[col] = round_up_f32(bnd);
+    }
+    best = block_max_f64(best, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = best;
+}
+
+// nrm_i >= ||a_i||_2 (float32, rounded up) from the header's 1/L_i, with the
+// relative margin `fac` for the rounding of L_i; part[blk] = the block's max.
+template <typename V>
+__global__ void __launch_bounds__(kBlock)
+k_col_norms(const char *__restrict__ seg, Layout lay, int64_t n, double fac, float *__restrict__ nrm,
+            double *__restrict__ part)
+{
+    __shared__ double lds[kBlock];
+    double best = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        int64_t off;
+        int32_t dp;
+        locate<V>(lay, i, off, dp);
+        const double il = reinterpret_cast<const double *>(seg + off)[1];
+        const double v = sqrt(1.0 / il) * fac;
+        const float u = round_up_f32(v);
+        nrm[i] = u;
+        best = fmax(best, (double)u);
+    }
+    best = block_max_f64(best, lds);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = best;
+}
+
+__global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst, int64_t len)
+{
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < len; j += (int64_t)gridDim.x * kBlock)
+        dst[j] = src[j];
+}
+
 // --------------------------------------------------------------------------
 // Set-up: validation and packing into the record layout.
 // --------------------------------------------------------------------------

@@ -124,7 +124,17 @@ struct pcdm_problem {
     double *part2 = nullptr;  // nblk_max
     float *t32 = nullptr;     // m: fl32(r64) for the bound pass of ||A^T r||_inf (values below float64)
     float *ub = nullptr;      // n: per-column upper bounds of that pass
-    int max_passes = 2;       // ||A^T r||_inf: 2 = bound + exact pass where available, 1 = one exact pass
+    int max_passes = 3;       // ||A^T r||_inf: 2 = bound + exact pass where available, 1 = one exact pass,
+                              // 3 = incremental from the last evaluation where it pays, else as 2
+    // incremental route: r of the last evaluation, column norms (rounded up),
+    // [M_old, sums, D, lower bound], candidate count; valid after a 2- or 3-route evaluation
+    double *rold = nullptr;
+    float *nrm = nullptr;
+    double *inc = nullptr;
+    unsigned long long *cnt = nullptr;
+    double nrm_max = 0.0, gam = 0.0;
+    bool inc_valid = false;
+    int64_t inc_hits = 0, inc_cands = -1;
 
     int timing = 0;
     KernelClock clocks[CLK_COUNT];
@@ -204,7 +214,7 @@ void free_problem(pcdm_problem *P)
         (void)hipEventDestroy(e);
     void *bufs[] = {P->seg, P->pc, P->x, P->r, P->r64, P->b64, P->id_slot,
                     P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim, P->bp, P->invlb, P->dx,
-                    P->t32, P->ub};
+                    P->t32, P->ub, P->rold, P->nrm, P->inc, P->cnt};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -571,7 +581,9 @@ template <typename V> struct Ops {
             // max_i ||A_i^T r64||_2: two passes as for the coordinate maximum
             // (bound over fl32(r64), exact norms of the candidate blocks), or one
             const int ga = grid_for(P->nb * 8, kBlock, P->nblk_max);
-            const bool two = !std::is_same<V, double>::value && P->t32 && P->ub && P->max_passes == 2;
+            const bool two = !std::is_same<V, double>::value && P->t32 && P->ub && P->max_passes != 1;
+            if (two)
+                P->inc_valid = false;  // ub will hold block bounds
             if (two) {
                 const int gm = grid_for(P->m, kBlock, P->nblk_max);
                 hipLaunchKernelGGL((k_narrow<float>), dim3(gm), dim3(kBlock), 0, s, (const double *)P->r64, P->t32,
@@ -692,7 +704,32 @@ template <typename V> struct Ops {
     static int atr_absmax(pcdm_problem *P, const double *rv, hipStream_t s)
     {
         const int grid = grid_for(P->n, kBlock, P->nblk_max);
+        const bool inc_route = P->max_passes == 3 && P->rold;
+        if (inc_route && P->inc_valid) {
+            // bounds moved from the last evaluation; taken when few columns remain
+            const int gm = grid_for(P->m, kBlock, kReduceBlocks);
+            hipLaunchKernelGGL(k_inc_sums, dim3(gm), dim3(kBlock), 0, s, rv, (const double *)P->rold, P->m, P->part);
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part, gm, 3, 0, P->inc + 1);
+            hipLaunchKernelGGL(k_inc_prepare, dim3(1), dim3(1), 0, s, P->inc, P->nrm_max, P->gam, (double)P->m);
+            hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(kBlock), 0, s, P->cnt, 0ull, (int64_t)1);
+            hipLaunchKernelGGL(k_inc_count, dim3(grid), dim3(kBlock), 0, s, (const float *)P->ub,
+                               (const float *)P->nrm, P->n, (const double *)P->inc, P->cnt);
+            unsigned long long c = 0;
+            HIP_TRY(hipMemcpyAsync(&c, P->cnt, 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            P->inc_cands = (int64_t)c;
+            if ((int64_t)c <= P->n / 8) {
+                P->inc_hits++;
+                hipLaunchKernelGGL((k_atr_inc<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                                   rv, P->n, P->ub, (const float *)P->nrm, (const double *)P->inc, P->part2);
+                hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
+                                   P->ctrl->scal + 3);
+                keep_state(P, rv, s);
+                return PCDM_OK;
+            }
+        }
         if (std::is_same<V, double>::value || !P->t32 || !P->ub || P->max_passes == 1) {
+            // touches neither ub nor the kept state
             hipLaunchKernelGGL((k_atr_absmax<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
                                rv, P->n, P->part2);
         } else {
@@ -707,6 +744,41 @@ template <typename V> struct Ops {
         }
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
                            P->ctrl->scal + 3);
+        if (!std::is_same<V, double>::value && P->t32 && P->ub && P->max_passes != 1) {
+            // ub now holds bounds for rv
+            if (inc_route)
+                keep_state(P, rv, s);
+            else
+                P->inc_valid = false;
+        }
+        return PCDM_OK;
+    }
+
+    // The incremental route's state after an evaluation at rv: r_old = rv,
+    // M_old = the result.
+    static void keep_state(pcdm_problem *P, const double *rv, hipStream_t s)
+    {
+        const int gm = grid_for(P->m, kBlock, P->nblk_max);
+        hipLaunchKernelGGL(k_copy_f64, dim3(gm), dim3(kBlock), 0, s, rv, P->rold, P->m);
+        hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(kBlock), 0, s, (const double *)(P->ctrl->scal + 3), P->inc,
+                           (int64_t)1);
+        P->inc_valid = true;
+    }
+
+    // Column norms for the incremental route (rounded up) and their maximum.
+    static int col_norms(pcdm_problem *P, hipStream_t s)
+    {
+        const int grid = grid_for(P->n, kBlock, P->nblk_max);
+        const double dmax = P->lay.fixed_dpad ? (double)P->lay.fixed_dpad : (double)P->m;
+        hipLaunchKernelGGL((k_col_norms<V>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, P->n,
+                           1.0 + (dmax + 8.0) * 0x1p-52, P->nrm, P->part2);
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
+                           P->ctrl->scal + 5);
+        double v = 0.0;
+        HIP_TRY(hipMemcpyAsync(&v, P->ctrl->scal + 5, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        P->nrm_max = v;
+        P->gam = (dmax + 2.0) * 0x1p-52;
         return PCDM_OK;
     }
 
@@ -952,6 +1024,10 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
     if (P->dtype != PCDM_F64) {
         HIP_TRY(hipMalloc(&P->t32, (size_t)A->m * 4));
         HIP_TRY(hipMalloc(&P->ub, (size_t)A->n * 4));
+        HIP_TRY(hipMalloc(&P->rold, (size_t)A->m * 8));
+        HIP_TRY(hipMalloc(&P->nrm, (size_t)A->n * 4));
+        HIP_TRY(hipMalloc(&P->inc, 8 * 8));
+        HIP_TRY(hipMalloc(&P->cnt, 8));
     }
     HIP_TRY(hipMemset(P->x, 0, (size_t)A->n * 8));
     HIP_TRY(hipMemcpy(P->b64, bdev, (size_t)A->m * 8, hipMemcpyDeviceToDevice));
@@ -1014,6 +1090,9 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
     P->lanes_auto = 1;
     compute_beta(P);
     P->refresh_every = ceil_div(P->n, P->tau);
+
+    if (P->nrm)
+        PCDM_TRY(dispatch(P->dtype, [&](auto ops) { return decltype(ops)::col_norms(P, s); }));
 
     // r = -b, ||A^T b||_inf.
     {
@@ -1316,8 +1395,8 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             return fail(PCDM_EINVAL, "graph_steps must be an integer in [0, 4096]");
         h->graph_len = (int64_t)value;
     } else if (k == "max_passes") {
-        if (value != 1.0 && value != 2.0)
-            return fail(PCDM_EINVAL, "max_passes must be 1 or 2");
+        if (value != 1.0 && value != 2.0 && value != 3.0)
+            return fail(PCDM_EINVAL, "max_passes must be 1, 2 or 3");
         h->max_passes = (int)value;
     } else if (k == "narrow_below") {
         if (!(value >= 0.0))
@@ -1397,6 +1476,8 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->upper = h->hi;
     out->async_picks = h->async_picks;
     out->async_processors = h->async_procs_last;
+    out->max_incremental = h->inc_hits;
+    out->max_candidates = h->inc_cands;
     return PCDM_OK;
 }
 

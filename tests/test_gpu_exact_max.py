@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import CSC, csc_to_dense, random_csc, random_csc_ragged
+from workloads import CSC, csc_to_dense, make_config, random_csc, random_csc_ragged
 
 pytestmark = pytest.mark.gpu
 
@@ -144,6 +144,73 @@ def test_max_passes_option_checked(pc):
     rng = np.random.default_rng(6)
     A = random_csc(50, 40, 3, rng).astype("f32")
     with pc.Problem(A, rng.standard_normal(50), 0.1, 2) as p:
-        for bad in (0, 3, 1.5):
+        for bad in (0, 4, 1.5):
             with pytest.raises(PCDMError):
                 p.set_option("max_passes", bad)
+
+
+def _sequence(pc, A, b, lam, xs, passes):
+    """(||A^T b||, F, gap) at each point of xs, evaluated in order on one
+    handle with the given route."""
+    out, cands = [], []
+    with pc.Problem(A, b, lam, 4, seed=0) as p:
+        p.set_option("max_passes", passes)
+        p.set_rhs(b)
+        for x in xs:
+            p.set_x(x, k=0)
+            out.append(p.objective(gap=True))
+            cands.append(p.info()["max_candidates"])
+        hits = p.info()["max_incremental"]
+    return out, hits, cands
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_incremental_route_equals_single_pass_along_a_sequence(pc, dtype):
+    """Route 3 keeps r and per-column bounds from the last evaluation and sums
+    exactly only the columns whose moved bound can still reach the maximum.
+    Along a sequence of nearby points (small and large moves, a move back,
+    no move) it returns the single pass's numbers bit for bit.  The points
+    are supported on columns sharing no row, so the float64 residual is the
+    same bits on every handle."""
+    rng = np.random.default_rng(11)
+    A = random_csc(1500, 1200, 6, rng).astype(dtype)
+    b = rng.standard_normal(1500)
+    sup = _disjoint_support(A, 150, rng)
+    x0 = np.zeros(1200)
+    x0[sup] = rng.standard_normal(sup.size)
+    xs = [x0]
+    for scale in (1e-6, 1e-3, 1e-6, 0.0, 1.0, 1e-9):
+        x = xs[-1].copy()
+        x[sup] += scale * rng.standard_normal(sup.size)
+        xs.append(x.astype(np.float32).astype(np.float64))
+    xs.append(xs[0])
+    one, hits1, _ = _sequence(pc, A, b, 0.2, xs, 1)
+    inc, hits3, cands = _sequence(pc, A, b, 0.2, xs, 3)
+    assert inc == one
+    assert hits1 == 0
+    # set_rhs's ||A^T b|| leaves the state the first point moves from (a large
+    # move: every column a candidate); the small moves and the unmoved point
+    # are decided from the moved bounds with few exact sums
+    assert hits3 >= 4 and max(cands[1], cands[2], cands[3], cands[4]) <= 1200 // 8, cands
+
+
+def test_incremental_route_after_steps(pc):
+    """Route 3 along a solve (steps between evaluations): the same objective
+    and gap as the single pass evaluated right after it at the same point, to
+    the refresh's rounding."""
+    inst = make_config("small_2000x1000", dtype="f32")
+    cands = []
+    with pc.Problem(inst.A, inst.b, inst.lam, 64, seed=1) as p:
+        for _ in range(12):
+            p.step(16 * 5)
+            p.set_option("max_passes", 3)
+            F3, g3 = p.objective(gap=True)
+            p.set_option("max_passes", 1)
+            F1, g1 = p.objective(gap=True)
+            cands.append(p.info()["max_candidates"])
+            # each evaluation refreshes the float64 residual with atomic adds,
+            # so the two see it to rounding only
+            assert F3 == pytest.approx(F1, rel=1e-13)
+            assert g3 == pytest.approx(g1, rel=1e-9, abs=1e-13 * abs(F1))
+        hits = p.info()["max_incremental"]
+    assert hits >= 1, cands

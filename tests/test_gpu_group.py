@@ -186,12 +186,12 @@ def test_gap_two_passes_equal_one(pc, dtype):
             used[rows] = True
             x[bp[i]:bp[i + 1]] = rng.standard_normal(bp[i + 1] - bp[i]).astype(np.float32)
     out = {}
-    for passes in (1, 2):
+    for passes in (1, 2, 3):
         with pc.Problem(A, b, 0.3, 5, seed=0, blocks=bp) as p:
             p.set_option("max_passes", passes)
             p.set_x(x)
             out[passes] = p.objective(gap=True)
-    assert out[1] == out[2], out
+    assert out[1] == out[2] == out[3], out
     ref = group.GroupSolver(A, b, 0.3, bp, tau=5, seed=0)
     ref.x = x.copy()
     gap_r, F_r, _ = ref.gap()

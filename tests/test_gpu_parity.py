@@ -330,11 +330,11 @@ def c2_full():
 
 def test_full_size_exact_max_routes_agree(pc, c2_full):
     """1e6 x 1e7: ||A^T b||_inf and the gap at x = 0 (r = -b exactly, no
-    atomics) are the same numbers by the two-pass and the single-pass route;
-    after steps the two routes agree to the float64 refresh's rounding."""
+    atomics) are the same numbers by the default and the single-pass route;
+    after steps the three routes agree to the float64 refresh's rounding."""
     inst = c2_full
     with pc.Problem(inst.A, inst.b, inst.lam, 1_000_000, seed=0) as p:
-        atb2 = p.info()["atb_inf"]  # at create: two passes
+        atb2 = p.info()["atb_inf"]  # at create: no kept state, two passes
         F2, g2 = p.objective(gap=True)
         p.set_option("max_passes", 1)
         p.set_rhs(inst.b)
@@ -343,10 +343,13 @@ def test_full_size_exact_max_routes_agree(pc, c2_full):
         assert (atb1, F1, g1) == (atb2, F2, g2)
         p.step(30)
         F1, g1 = p.objective(gap=True)
-        p.set_option("max_passes", 2)
-        F2, g2 = p.objective(gap=True)
-    assert F2 == pytest.approx(F1, rel=1e-13)
-    assert g2 == pytest.approx(g1, rel=1e-10)
+        for passes in (2, 3, 3):
+            # the second route-3 evaluation moves from the first one's state
+            p.set_option("max_passes", passes)
+            F2, g2 = p.objective(gap=True)
+            assert F2 == pytest.approx(F1, rel=1e-13)
+            assert g2 == pytest.approx(g1, rel=1e-10)
+        assert p.info()["max_incremental"] >= 1
 
 
 def test_full_size_steps_match_oracle(pc, c2_full):
