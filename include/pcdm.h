@@ -272,7 +272,7 @@ const char *pcdm_last_error(void);
  *                      over fl32(r) giving every column (block) a rigorous
  *                      bound, then the exact float64 sums for the columns
  *                      (blocks) whose bound reaches the largest lower bound;
- *                      1 = the exact sums everywhere; 3 (default) = as 2, keeping r and
+ *                      1 = the exact sums everywhere; 3 = as 2, keeping r and
  *                      the bounds of the last evaluation: the next one moves
  *                      each column's bound by ||a_i||_2 times a rigorous bound
  *                      on the change of r (Cauchy-Schwarz) and, when at most
@@ -280,7 +280,9 @@ const char *pcdm_last_error(void);
  *                      those exactly (one pass over r and the candidate
  *                      records; the host reads the candidate count).  All
  *                      three give the same number; float64 values always
- *                      take one pass, blocks take 2 for 3;
+ *                      take one pass, blocks take 2 for 3; 0 (default) = 3
+ *                      from 2^24 stored entries, else 2 (below that the
+ *                      route's fixed costs exceed a bound pass);
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
  *                      settings of pcdm_grad_backward's solve (see there);
@@ -470,11 +472,17 @@ int pcdm_batch_set_active(pcdm_batch *B, const int32_t *active);
 int pcdm_batch_get_x(pcdm_batch *B, int index, double *x_out, int32_t on_device, void *stream);
 
 /* Sizes, omega, beta, lambda, ||A^T b||_inf, steps taken of problem `index`
- * (nonzero_updates is -1: not tracked per problem). */
+ * (nonzero_updates is -1: not tracked per problem); max_incremental counts
+ * its evaluations that moved kept bounds, max_candidates the columns its
+ * last evaluation summed. */
 int pcdm_batch_get_info(pcdm_batch *B, int index, pcdm_info *out);
 
 /* Options: "graph_steps" (>= 0), "lanes_per_column", "chunks_per_lane"
- * (pairs as for pcdm_set_option). */
+ * (pairs as for pcdm_set_option), "max_passes": 3 (default) = each problem
+ * keeps r and per-column bounds of its last evaluation and sums exactly only
+ * the columns whose moved bound can still reach its maximum (as route 3 of
+ * pcdm_set_option, without the fallback: the pass itself skips the others);
+ * 1 or 2 = every column summed.  Both give the same numbers. */
 int pcdm_batch_set_option(pcdm_batch *B, const char *key, double value);
 
 /* Schedule autotuner for the batch (as pcdm_autotune; the steps advance

@@ -272,78 +272,105 @@ k_batch_narrow(const BatchInst *__restrict__ desc, BatchList L, const double *__
 
 // Per-problem objective pieces of the listed problems: acc[4j+0] +=
 // ||r64||^2, acc[4j+1] += b.r64 (rows) and acc[4j+2] += ||x||_1 (columns, see
-// k_batch_col_obj).
+// k_batch_col_obj).  For the incremental maximum also dacc[3j+0] +=
+// ||r64 - rold||^2 and dacc[3j+1] += ||rold||^2, after which rold = r64.
+// Each wave takes a contiguous run of row tiles and keeps per-lane partial
+// sums while the problem stays the same: the per-problem atomics go to a
+// handful of addresses, so they are issued once per (wave, problem) rather
+// than once per tile.
 __global__ void __launch_bounds__(kBlock)
 k_batch_row_sums(const BatchInst *__restrict__ desc, BatchList L, const double *__restrict__ b,
-                 const double *__restrict__ r64, double *__restrict__ acc)
+                 const double *__restrict__ r64, double *__restrict__ acc, double *__restrict__ rold,
+                 double *__restrict__ dacc)
 {
     __shared__ int64_t lds[kMaxListLds];
     const ListView v = load_list(L, L.rowp, lds);
     const int lane = threadIdx.x & 63;
-    for (int64_t t = wave_global_id(); t < v.total(); t += wave_count()) {
-        const int q = v.find(t);
-        const int j = v.ids[q];
-        const BatchInst &d = desc[j];
-        const int64_t row = (t - v.p[q]) * 64 + lane;
-        double rr = 0.0, br = 0.0;
-        if (row < d.m) {
-            const double x = r64[d.row_base + row];
-            rr = x * x;
-            br = b[d.row_base + row] * x;
-        }
+    const int64_t T = v.total();
+    const int64_t per = (T + wave_count() - 1) / wave_count();
+    const int64_t t0 = wave_global_id() * per;
+    const int64_t t1 = t0 + per < T ? t0 + per : T;
+    double rr = 0.0, br = 0.0, dd = 0.0, oo = 0.0;
+    int q = -1;
+    int64_t qend = 0;
+    auto flush = [&]() {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             rr += __shfl_xor(rr, o, 64);
             br += __shfl_xor(br, o, 64);
+            dd += __shfl_xor(dd, o, 64);
+            oo += __shfl_xor(oo, o, 64);
         }
         if (lane == 0) {
+            const int j = v.ids[q];
             atomic_add_hw<double>(acc + 4 * j + 0, rr);
             atomic_add_hw<double>(acc + 4 * j + 1, br);
+            atomic_add_hw<double>(dacc + 3 * j + 0, dd);
+            atomic_add_hw<double>(dacc + 3 * j + 1, oo);
+        }
+        rr = br = dd = oo = 0.0;
+    };
+    for (int64_t t = t0; t < t1; ++t) {
+        if (t >= qend) {  // wave-uniform: next problem
+            if (q >= 0)
+                flush();
+            q = v.find(t);
+            qend = v.p[q + 1];
+        }
+        const BatchInst &d = desc[v.ids[q]];
+        const int64_t row = (t - v.p[q]) * 64 + lane;
+        if (row < d.m) {
+            const int64_t g = d.row_base + row;
+            const double x = r64[g], o = rold[g];
+            rr += x * x;
+            br += b[g] * x;
+            dd += (x - o) * (x - o);
+            oo += o * o;
+            rold[g] = x;
         }
     }
+    if (q >= 0)
+        flush();
 }
 
 // acc[4j+2] += ||x_j||_1 and acc[4j+3] = max(|a_i^T r64|) over the columns
 // of the listed problems.  The max goes through the unsigned bit pattern
-// (monotone for values >= 0).
+// (monotone for values >= 0).  Contiguous tile runs per wave, as in
+// k_batch_row_sums.
+//
+// Incremental maximum (ist[4j] = M_old, the maximum of the last evaluation
+// at rold; ist[4j+1] >= max_i ||a_i||_2; ist[4j+3] != 0 once that state
+// exists; ub[i] >= |the computed sum of column i| at rold): every computed
+// float64 sum moves by at most ||a_i||_2 D, D = ||r - rold||_2 + 2 gamma
+// max(||r||_2, ||rold||_2), gamma = (d + 2) 2^-52 covering the summation
+// rounding at either point.  A column whose moved bound stays below
+// M_old - max_i ||a_i||_2 D (a lower bound of the new maximum) cannot attain
+// it and is not summed; the others are summed exactly as in the full pass,
+// so the maximum is the same number.  ub is moved (non-candidates) or set
+// to the computed value (candidates), rounded up; dacc[3j+2] counts the
+// candidates.
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
 k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc, BatchList L,
-                const double *__restrict__ xm, const double *__restrict__ r64, double *__restrict__ acc)
+                const double *__restrict__ xm, const double *__restrict__ r64, double *__restrict__ acc,
+                float *__restrict__ ub, const float *__restrict__ nrm, const double *__restrict__ ist,
+                double *__restrict__ dacc, int incremental)
 {
     using T = typename ValT<V>::T;
     __shared__ int64_t lds[kMaxListLds];
     const ListView v = load_list(L, L.colp, lds);
     const TileLanes<G> tl;
-    for (int64_t t = wave_global_id(); t < v.total(); t += wave_count()) {
-        const int q = v.find(t);
-        const int j = v.ids[q];
-        const BatchInst &d = desc[j];
-        const int64_t col = (t - v.p[q]) * 64 + tl.lane;
-        int64_t off = 0;
-        int32_t dp = 0;
-        double ax = 0.0;
-        if (col < d.n) {
-            locate<V>(d.lay, col, off, dp);
-            ax = fabs(xm[d.col_base + col]);
-        }
-        double a[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-            a[g] = 0.0;
-        const double *rr = r64 + d.row_base;
-        tile_entries<V, G>(seg + d.rec_base, tl, off, dp, 0, [&](int g, int, int row, T val) {
-            a[g] += (double)val * rr[row];
-        });
-        double mine = 0.0;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const double sq = group_sum<G>(a[g]);
-            const double got = __shfl(sq, tl.leader_of_mine(g));
-            if (tl.lane / TileLanes<G>::CPR == g)
-                mine = got;
-        }
-        double gm = col < d.n ? fabs(mine) : 0.0;
+    const int64_t NT = v.total();
+    const int64_t per = (NT + wave_count() - 1) / wave_count();
+    const int64_t t0 = wave_global_id() * per;
+    const int64_t t1 = t0 + per < NT ? t0 + per : NT;
+    double ax = 0.0, gm = 0.0;
+    int ncand = 0;
+    int q = -1, j = 0;
+    int64_t qend = 0;
+    bool inc = false;
+    double D = 0.0, lo = 0.0;
+    auto flush = [&]() {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             ax += __shfl_xor(ax, o, 64);
@@ -353,7 +380,87 @@ k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc
             atomic_add_hw<double>(acc + 4 * j + 2, ax);
             atomicMax(reinterpret_cast<unsigned long long *>(acc + 4 * j + 3),
                       (unsigned long long)__double_as_longlong(gm));
+            if (ncand)
+                atomic_add_hw<double>(dacc + 3 * j + 2, (double)ncand);
         }
+        ax = gm = 0.0;
+        ncand = 0;
+    };
+    for (int64_t t = t0; t < t1; ++t) {
+        if (t >= qend) {  // wave-uniform: next problem
+            if (q >= 0)
+                flush();
+            q = v.find(t);
+            qend = v.p[q + 1];
+            j = v.ids[q];
+            const BatchInst &d = desc[j];
+            inc = incremental && ist[4 * j + 3] != 0.0;
+            if (inc) {
+                const double dmax = d.lay.fixed_dpad ? (double)d.lay.fixed_dpad : (double)d.m;
+                const double gam = (dmax + 2.0) * 0x1p-52;
+                // each sum of m nonnegative terms is within (m + 4) 2^-52 of its exact value
+                const double up = 1.0 + ((double)d.m + 4.0) * 0x1p-52;
+                const double dlt = sqrt(dacc[3 * j] * up) * (1.0 + 0x1p-50);
+                const double rmax = sqrt(fmax(acc[4 * j], dacc[3 * j + 1]) * up) * (1.0 + 0x1p-50);
+                D = (dlt + 2.0 * gam * rmax) * (1.0 + 0x1p-40);
+                lo = (ist[4 * j] - ist[4 * j + 1] * D) * (1.0 - 0x1p-40) - 0x1p-1000;
+            }
+        }
+        const BatchInst &d = desc[j];
+        const int64_t col = (t - v.p[q]) * 64 + tl.lane;
+        int64_t off = 0;
+        int32_t dp = 0;
+        double bnd = 0.0;
+        bool cand = false;
+        if (col < d.n) {
+            ax += fabs(xm[d.col_base + col]);
+            cand = true;
+            if (inc) {
+                bnd = (double)ub[d.col_base + col] * (1.0 + 0x1p-40) + (double)nrm[d.col_base + col] * D;
+                cand = !(bnd < lo);
+            }
+            if (cand)
+                locate<V>(d.lay, col, off, dp);
+        }
+        const int nc = __popcll(__ballot(cand));
+        ncand += nc;
+        if (nc) {
+            double a[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                a[g] = 0.0;
+            const double *rr = r64 + d.row_base;
+            tile_entries<V, G>(seg + d.rec_base, tl, off, dp, 0, [&](int g, int, int row, T val) {
+                a[g] += (double)val * rr[row];
+            });
+            double mine = 0.0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const double sq = group_sum<G>(a[g]);
+                const double got = __shfl(sq, tl.leader_of_mine(g));
+                if (tl.lane / TileLanes<G>::CPR == g)
+                    mine = got;
+            }
+            if (cand) {
+                gm = fmax(gm, fabs(mine));
+                bnd = fabs(mine);
+            }
+        }
+        if (col < d.n)
+            ub[d.col_base + col] = round_up_f32(bnd);
+    }
+    if (q >= 0)
+        flush();
+}
+
+// After an objective pass: the listed problems' maxima become M_old.
+__global__ void k_batch_keep_max(BatchList L, const double *__restrict__ acc, double *__restrict__ ist)
+{
+    const int cnt = *L.n;
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+        const int j = L.ids[q];
+        ist[4 * j + 0] = acc[4 * j + 3];
+        ist[4 * j + 3] = 1.0;
     }
 }
 

@@ -17,7 +17,14 @@ struct pcdm_batch {
 
     char *seg = nullptr;
     int64_t *pc_all = nullptr;
-    double *x = nullptr, *r64 = nullptr, *b = nullptr, *acc = nullptr;
+    double *x = nullptr, *r64 = nullptr, *b = nullptr, *acc = nullptr;  // acc: 4 + 3 per problem
+    // incremental ||A_j^T r_j||_inf: r of the last evaluation, per-column
+    // upper bounds and norms (rounded up), per problem [M_old, max norm, -, valid]
+    double *rold = nullptr, *ist = nullptr;
+    float *ubc = nullptr, *nrmc = nullptr;
+    int incremental = 1;
+    std::vector<int64_t> inc_evals, cands;  // per problem: evaluations that moved bounds, last candidates
+    std::vector<char> inc_state;
     void *r = nullptr, *delta_slot = nullptr;
     int32_t *id_slot = nullptr, *active = nullptr;
     BatchInst *desc = nullptr;
@@ -62,7 +69,8 @@ void batch_free(pcdm_batch *B)
     if (!B)
         return;
     batch_drop_graph(B);
-    void *bufs[] = {B->seg, B->pc_all, B->x, B->r64, B->b, B->acc, B->r, B->delta_slot, B->id_slot, B->active,
+    void *bufs[] = {B->seg, B->pc_all, B->x, B->r64, B->b, B->acc, B->rold, B->ist, B->ubc, B->nrmc,
+                    B->r, B->delta_slot, B->id_slot, B->active,
                     B->desc, B->step_tiles, B->nz_part, B->sel, B->list.n, B->list.ids, B->list.colp,
                     B->list.rowp};
     for (void *q : bufs)
@@ -135,13 +143,29 @@ template <typename V> struct BatchOps {
     {
         list(B, s, B->sel);
         refresh(B, s);
-        hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, s, B->acc, 0.0, (int64_t)4 * B->count);
+        double *dacc = B->acc + 4 * (int64_t)B->count;
+        hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, s, B->acc, 0.0, (int64_t)7 * B->count);
         hipLaunchKernelGGL(k_batch_row_sums, dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)),
                            dim3(kBlock), 0, s, (const BatchInst *)B->desc, B->list, (const double *)B->b,
-                           (const double *)B->r64, B->acc);
+                           (const double *)B->r64, B->acc, B->rold, dacc);
         hipLaunchKernelGGL((k_batch_col_obj<V, 8>), dim3(grid_for(B->n_col_tiles * 64, kBlock, B->nblk_max)),
                            dim3(kBlock), 0, s, (const char *)B->seg, (const BatchInst *)B->desc, B->list,
-                           (const double *)B->x, (const double *)B->r64, B->acc);
+                           (const double *)B->x, (const double *)B->r64, B->acc, B->ubc, (const float *)B->nrmc,
+                           (const double *)B->ist, dacc, B->incremental);
+        hipLaunchKernelGGL(k_batch_keep_max, dim3(1), dim3(kBlock), 0, s, B->list, (const double *)B->acc,
+                           B->ist);
+    }
+
+    // nrmc of problem j's columns (>= ||a_i||_2, float32 rounded up) and
+    // ist[4j+1] = their maximum.
+    static void col_norms(pcdm_batch *B, int j, double *part, hipStream_t s)
+    {
+        const BatchInst &d = B->hdesc[j];
+        const double dmax = d.lay.fixed_dpad ? (double)d.lay.fixed_dpad : (double)d.m;
+        const int g = grid_for(d.n, kBlock, B->nblk_max);
+        hipLaunchKernelGGL((k_col_norms<V>), dim3(g), dim3(kBlock), 0, s, (const char *)B->seg + d.rec_base, d.lay,
+                           d.n, 1.0 + (dmax + 8.0) * 0x1p-52, B->nrmc + d.col_base, part);
+        hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, g, 1, 1, B->ist + 4 * j + 1);
     }
 
     static void narrow_all(pcdm_batch *B, hipStream_t s)
@@ -365,7 +389,13 @@ int batch_create_impl(int count, const pcdm_csc *A, const double *const *b, cons
     HIP_TRY(hipMalloc(&B->delta_slot, (size_t)slot_base * B->tbytes));
     HIP_TRY(hipMalloc(&B->desc, sizeof(BatchInst) * count));
     HIP_TRY(hipMalloc(&B->active, 4 * (size_t)count));
-    HIP_TRY(hipMalloc(&B->acc, 32 * (size_t)count));
+    HIP_TRY(hipMalloc(&B->acc, 56 * (size_t)count));
+    HIP_TRY(hipMalloc(&B->rold, (size_t)row_base * 8));
+    HIP_TRY(hipMemset(B->rold, 0, (size_t)row_base * 8));
+    HIP_TRY(hipMalloc(&B->ubc, (size_t)col_base * 4));
+    HIP_TRY(hipMalloc(&B->nrmc, (size_t)col_base * 4));
+    HIP_TRY(hipMalloc(&B->ist, 32 * (size_t)count));
+    HIP_TRY(hipMemset(B->ist, 0, 32 * (size_t)count));
     HIP_TRY(hipMalloc(&B->nz_part, 8 * (size_t)B->nblk_max));
     HIP_TRY(hipMemset(B->nz_part, 0, 8 * (size_t)B->nblk_max));
     {
@@ -387,6 +417,9 @@ int batch_create_impl(int count, const pcdm_csc *A, const double *const *b, cons
         B->cG.assign(count, 0.0);
         B->ck.assign(count, -1);
         B->cvalid.assign(count, 0);
+        B->inc_evals.assign(count, 0);
+        B->cands.assign(count, -1);
+        B->inc_state.assign(count, 1);  // set by the evaluation at create
     }
 
     // pass 2: pack every problem, omega_j, b_j
@@ -405,13 +438,14 @@ int batch_create_impl(int count, const pcdm_csc *A, const double *const *b, cons
         }
         HIP_TRY(hipMemset(ctrl, 0, sizeof(Ctrl)));
         HIP_TRY(hipMemset(hist, 0, (size_t)a.m * 4));
-        batch_dispatch(dtype, [&](auto ops) {
-            decltype(ops)::pack(B, cp, rw, vl, j, hist, ctrl, s);
-            return PCDM_OK;
-        });
         const int gm = grid_for(a.m, kBlock, B->nblk_max);
         int64_t *part = nullptr;
-        PCDM_TRY(guard.tmp.get(&part, (size_t)gm * 8));
+        PCDM_TRY(guard.tmp.get(&part, (size_t)std::max(gm, B->nblk_max) * 8));
+        batch_dispatch(dtype, [&](auto ops) {
+            decltype(ops)::pack(B, cp, rw, vl, j, hist, ctrl, s);
+            decltype(ops)::col_norms(B, j, reinterpret_cast<double *>(part), s);
+            return PCDM_OK;
+        });
         hipLaunchKernelGGL(k_imax_partials, dim3(gm), dim3(kBlock), 0, s, (const int32_t *)hist, a.m, part);
         hipLaunchKernelGGL(k_imax_final, dim3(1), dim3(kBlock), 0, s, (const int64_t *)part, gm, ctrl);
         PCDM_TRY(check_launch("batch k_pack"));
@@ -518,7 +552,7 @@ int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream)
         B->hsel[j] = (!B->cvalid[j] || B->ck[j] != B->k_host[j]) ? 1 : 0;
         any = any || B->hsel[j];
     }
-    std::vector<double> acc(4 * (size_t)B->count, 0.0);
+    std::vector<double> acc(7 * (size_t)B->count, 0.0);
     if (any) {
         HIP_TRY(hipMemcpyAsync(B->sel, B->hsel.data(), 4 * (size_t)B->count, hipMemcpyHostToDevice, s));
         PCDM_TRY(batch_dispatch(B->dtype, [&](auto ops) {
@@ -526,7 +560,7 @@ int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream)
             return PCDM_OK;
         }));
         PCDM_TRY(check_launch("pcdm_batch_objective"));
-        HIP_TRY(hipMemcpyAsync(acc.data(), B->acc, 32 * (size_t)B->count, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(acc.data(), B->acc, 56 * (size_t)B->count, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
     for (int j = 0; j < B->count; ++j) {
@@ -539,6 +573,9 @@ int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream)
             B->cG[j] = Fj - (-0.5 * sc * sc * rr - sc * br);
             B->ck[j] = B->k_host[j];
             B->cvalid[j] = 1;
+            B->cands[j] = (int64_t)acc[4 * (size_t)B->count + 3 * j + 2];
+            if (B->incremental && B->inc_state[j])
+                B->inc_evals[j]++;
         }
         F[j] = B->cF[j];
         if (gap)
@@ -594,6 +631,8 @@ int pcdm_batch_get_info(pcdm_batch *B, int index, pcdm_info *out)
     out->lanes_per_column = B->lanes;
     out->chunks_per_lane = B->chunks;
     out->nonzero_updates = -1;  // not tracked per problem
+    out->max_incremental = B->inc_evals[index];
+    out->max_candidates = B->cands[index];
     return PCDM_OK;
 }
 
@@ -608,6 +647,10 @@ int pcdm_batch_set_option(pcdm_batch *B, const char *key, double value)
     if (k == "graph_steps") {
         B->graph_len = v;
         batch_drop_graph(B);
+    } else if (k == "max_passes") {
+        if (v < 1 || v > 3)
+            return fail(PCDM_EINVAL, "max_passes must be 1, 2 or 3");
+        B->incremental = v == 3;
     } else if (k == "lanes_per_column" || k == "chunks_per_lane") {
         const int g = k == "lanes_per_column" ? v : B->lanes;
         const int c = k == "chunks_per_lane" ? v : (schedule_supported(v, B->chunks) ? B->chunks : 1);

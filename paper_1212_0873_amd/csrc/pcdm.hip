@@ -124,8 +124,9 @@ struct pcdm_problem {
     double *part2 = nullptr;  // nblk_max
     float *t32 = nullptr;     // m: fl32(r64) for the bound pass of ||A^T r||_inf (values below float64)
     float *ub = nullptr;      // n: per-column upper bounds of that pass
-    int max_passes = 3;       // ||A^T r||_inf: 2 = bound + exact pass where available, 1 = one exact pass,
-                              // 3 = incremental from the last evaluation where it pays, else as 2
+    int max_passes = 0;       // ||A^T r||_inf: 2 = bound + exact pass where available, 1 = one exact pass,
+                              // 3 = incremental from the last evaluation where it pays, else as 2,
+                              // 0 = 3 from kIncMinEntries stored entries, else 2
     // incremental route: r of the last evaluation, column norms (rounded up),
     // [M_old, sums, D, lower bound], candidate count; valid after a 2- or 3-route evaluation
     double *rold = nullptr;
@@ -184,6 +185,17 @@ struct pcdm_problem {
     double adj_last_resid = 0.0;
     std::vector<hipEvent_t> event_pool;
 };
+
+namespace {
+// Below this many stored entries the incremental route's fixed costs (its
+// extra launches and the host read of the candidate count) exceed a bound
+// pass, so the automatic choice (max_passes 0) takes the two-pass route.
+constexpr int64_t kIncMinEntries = int64_t(1) << 24;
+inline int passes(const pcdm_problem *P)
+{
+    return P->max_passes ? P->max_passes : (P->stored_nnz >= kIncMinEntries ? 3 : 2);
+}
+}  // namespace
 
 namespace {
 
@@ -581,7 +593,7 @@ template <typename V> struct Ops {
             // max_i ||A_i^T r64||_2: two passes as for the coordinate maximum
             // (bound over fl32(r64), exact norms of the candidate blocks), or one
             const int ga = grid_for(P->nb * 8, kBlock, P->nblk_max);
-            const bool two = !std::is_same<V, double>::value && P->t32 && P->ub && P->max_passes != 1;
+            const bool two = !std::is_same<V, double>::value && P->t32 && P->ub && passes(P) != 1;
             if (two)
                 P->inc_valid = false;  // ub will hold block bounds
             if (two) {
@@ -704,7 +716,8 @@ template <typename V> struct Ops {
     static int atr_absmax(pcdm_problem *P, const double *rv, hipStream_t s)
     {
         const int grid = grid_for(P->n, kBlock, P->nblk_max);
-        const bool inc_route = P->max_passes == 3 && P->rold;
+        const int mp = passes(P);
+        const bool inc_route = mp == 3 && P->rold;
         if (inc_route && P->inc_valid) {
             // bounds moved from the last evaluation; taken when few columns remain
             const int gm = grid_for(P->m, kBlock, kReduceBlocks);
@@ -728,7 +741,7 @@ template <typename V> struct Ops {
                 return PCDM_OK;
             }
         }
-        if (std::is_same<V, double>::value || !P->t32 || !P->ub || P->max_passes == 1) {
+        if (std::is_same<V, double>::value || !P->t32 || !P->ub || mp == 1) {
             // touches neither ub nor the kept state
             hipLaunchKernelGGL((k_atr_absmax<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
                                rv, P->n, P->part2);
@@ -744,7 +757,7 @@ template <typename V> struct Ops {
         }
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
                            P->ctrl->scal + 3);
-        if (!std::is_same<V, double>::value && P->t32 && P->ub && P->max_passes != 1) {
+        if (!std::is_same<V, double>::value && P->t32 && P->ub && mp != 1) {
             // ub now holds bounds for rv
             if (inc_route)
                 keep_state(P, rv, s);
@@ -1395,8 +1408,8 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             return fail(PCDM_EINVAL, "graph_steps must be an integer in [0, 4096]");
         h->graph_len = (int64_t)value;
     } else if (k == "max_passes") {
-        if (value != 1.0 && value != 2.0 && value != 3.0)
-            return fail(PCDM_EINVAL, "max_passes must be 1, 2 or 3");
+        if (value != 0.0 && value != 1.0 && value != 2.0 && value != 3.0)
+            return fail(PCDM_EINVAL, "max_passes must be 0, 1, 2 or 3");
         h->max_passes = (int)value;
     } else if (k == "narrow_below") {
         if (!(value >= 0.0))

@@ -108,3 +108,37 @@ def _scipy_gap(A, b, x, lam):
     F = 0.5 * r @ r + lam * np.abs(x).sum()
     D = -0.5 * s * s * (r @ r) - s * (b @ r)
     return F - D, D
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_batch_gap_incremental_max(pc, dtype):
+    """The batched gap takes ||A_j^T r_j||_inf from the columns whose kept
+    bound, moved by ||a_i|| times the change of r, can still reach the
+    maximum.  At every check it equals the gap computed by scipy at the
+    batch's own x (to the float64 refresh's rounding), late checks sum only
+    a fraction of the columns, and the full pass (max_passes = 1) on a second
+    handle that follows the same float64 trajectory gives the same gaps."""
+    probs = _problems(dtype, seed=5)
+    total_n = sum(A.n for A, _, _, _ in probs)
+    cands = []
+    with pc.Batch(probs, seed=2) as B:
+        for rnd in range(10):
+            B.step(25 if rnd < 8 else 1)  # the last two checks: one step apart
+            F, gap = B.objective()
+            for j, (A, b, lam, tau) in enumerate(probs):
+                g_ref, _ = _scipy_gap(A, b, B.get_x(j), lam)
+                assert gap[j] == pytest.approx(g_ref, rel=1e-8, abs=1e-12 * abs(F[j])), (rnd, j)
+            cands.append(sum(B.info(j)["max_candidates"] for j in range(len(probs))))
+        hits = [B.info(j)["max_incremental"] for j in range(len(probs))]
+    assert min(hits) == 10, hits
+    assert max(cands) <= total_n and cands[-1] < total_n // 4, (cands, total_n)
+    if dtype == "f64":
+        # float64 steps: both handles follow the oracle's trajectory to 1e-9
+        with pc.Batch(probs, seed=2) as B1:
+            B1.set_option("max_passes", 1)
+            for rnd in range(10):
+                B1.step(25 if rnd < 8 else 1)
+                F1, gap1 = B1.objective()
+            assert all(B1.info(j)["max_incremental"] == 0 for j in range(len(probs)))
+            assert all(B1.info(j)["max_candidates"] == A.n for j, (A, _, _, _) in enumerate(probs))
+        np.testing.assert_allclose(gap1, gap, rtol=1e-7, atol=1e-12 * np.abs(F).max())

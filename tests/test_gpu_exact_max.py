@@ -144,7 +144,7 @@ def test_max_passes_option_checked(pc):
     rng = np.random.default_rng(6)
     A = random_csc(50, 40, 3, rng).astype("f32")
     with pc.Problem(A, rng.standard_normal(50), 0.1, 2) as p:
-        for bad in (0, 4, 1.5):
+        for bad in (-1, 4, 1.5):
             with pytest.raises(PCDMError):
                 p.set_option("max_passes", bad)
 
