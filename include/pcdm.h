@@ -274,8 +274,8 @@ const char *pcdm_last_error(void);
  *                      (blocks) whose bound reaches the largest lower bound;
  *                      1 = the exact sums everywhere; 3 = as 2, keeping r and
  *                      the bounds of the last evaluation: the next one moves
- *                      each column's bound by ||a_i||_2 times a rigorous bound
- *                      on the change of r (Cauchy-Schwarz) and, when at most
+ *                      each column's bound by ||a_i||_1 times a rigorous bound
+ *                      on the change of r in max norm (Hoelder) and, when at most
  *                      n/8 columns can still reach the maximum, sums only
  *                      those exactly (one pass over r and the candidate
  *                      records; the host reads the candidate count).  All

@@ -272,8 +272,9 @@ k_batch_narrow(const BatchInst *__restrict__ desc, BatchList L, const double *__
 
 // Per-problem objective pieces of the listed problems: acc[4j+0] +=
 // ||r64||^2, acc[4j+1] += b.r64 (rows) and acc[4j+2] += ||x||_1 (columns, see
-// k_batch_col_obj).  For the incremental maximum also dacc[3j+0] +=
-// ||r64 - rold||^2 and dacc[3j+1] += ||rold||^2, after which rold = r64.
+// k_batch_col_obj).  For the incremental maximum also dacc[4j+0] =
+// max |r64 - rold|, dacc[4j+1] = max |rold| and dacc[4j+3] = max |r64|
+// (maxima of values >= 0 through their bit patterns), after which rold = r64.
 // Each wave takes a contiguous run of row tiles and keeps per-lane partial
 // sums while the problem stays the same: the per-problem atomics go to a
 // handful of addresses, so they are issued once per (wave, problem) rather
@@ -290,25 +291,30 @@ k_batch_row_sums(const BatchInst *__restrict__ desc, BatchList L, const double *
     const int64_t per = (T + wave_count() - 1) / wave_count();
     const int64_t t0 = wave_global_id() * per;
     const int64_t t1 = t0 + per < T ? t0 + per : T;
-    double rr = 0.0, br = 0.0, dd = 0.0, oo = 0.0;
+    double rr = 0.0, br = 0.0, dd = 0.0, oo = 0.0, xx = 0.0;
     int q = -1;
     int64_t qend = 0;
+    auto amax = [](double *p, double v) {
+        atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+    };
     auto flush = [&]() {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             rr += __shfl_xor(rr, o, 64);
             br += __shfl_xor(br, o, 64);
-            dd += __shfl_xor(dd, o, 64);
-            oo += __shfl_xor(oo, o, 64);
+            dd = fmax(dd, __shfl_xor(dd, o, 64));
+            oo = fmax(oo, __shfl_xor(oo, o, 64));
+            xx = fmax(xx, __shfl_xor(xx, o, 64));
         }
         if (lane == 0) {
             const int j = v.ids[q];
             atomic_add_hw<double>(acc + 4 * j + 0, rr);
             atomic_add_hw<double>(acc + 4 * j + 1, br);
-            atomic_add_hw<double>(dacc + 3 * j + 0, dd);
-            atomic_add_hw<double>(dacc + 3 * j + 1, oo);
+            amax(dacc + 4 * j + 0, dd);
+            amax(dacc + 4 * j + 1, oo);
+            amax(dacc + 4 * j + 3, xx);
         }
-        rr = br = dd = oo = 0.0;
+        rr = br = dd = oo = xx = 0.0;
     };
     for (int64_t t = t0; t < t1; ++t) {
         if (t >= qend) {  // wave-uniform: next problem
@@ -324,8 +330,9 @@ k_batch_row_sums(const BatchInst *__restrict__ desc, BatchList L, const double *
             const double x = r64[g], o = rold[g];
             rr += x * x;
             br += b[g] * x;
-            dd += (x - o) * (x - o);
-            oo += o * o;
+            dd = fmax(dd, fabs(x - o));
+            oo = fmax(oo, fabs(o));
+            xx = fmax(xx, fabs(x));
             rold[g] = x;
         }
     }
@@ -339,15 +346,15 @@ k_batch_row_sums(const BatchInst *__restrict__ desc, BatchList L, const double *
 // k_batch_row_sums.
 //
 // Incremental maximum (ist[4j] = M_old, the maximum of the last evaluation
-// at rold; ist[4j+1] >= max_i ||a_i||_2; ist[4j+3] != 0 once that state
+// at rold; ist[4j+1] >= max_i ||a_i||_1; ist[4j+3] != 0 once that state
 // exists; ub[i] >= |the computed sum of column i| at rold): every computed
-// float64 sum moves by at most ||a_i||_2 D, D = ||r - rold||_2 + 2 gamma
-// max(||r||_2, ||rold||_2), gamma = (d + 2) 2^-52 covering the summation
-// rounding at either point.  A column whose moved bound stays below
-// M_old - max_i ||a_i||_2 D (a lower bound of the new maximum) cannot attain
+// float64 sum moves by at most ||a_i||_1 D, D = ||r - rold||_inf + 2 gamma
+// max(||r||_inf, ||rold||_inf) (Hoelder), gamma = (d + 2) 2^-52 covering the
+// summation rounding at either point.  A column whose moved bound stays below
+// M_old - max_i ||a_i||_1 D (a lower bound of the new maximum) cannot attain
 // it and is not summed; the others are summed exactly as in the full pass,
 // so the maximum is the same number.  ub is moved (non-candidates) or set
-// to the computed value (candidates), rounded up; dacc[3j+2] counts the
+// to the computed value (candidates), rounded up; dacc[4j+2] counts the
 // candidates.
 template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
@@ -381,7 +388,7 @@ k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc
             atomicMax(reinterpret_cast<unsigned long long *>(acc + 4 * j + 3),
                       (unsigned long long)__double_as_longlong(gm));
             if (ncand)
-                atomic_add_hw<double>(dacc + 3 * j + 2, (double)ncand);
+                atomic_add_hw<double>(dacc + 4 * j + 2, (double)ncand);
         }
         ax = gm = 0.0;
         ncand = 0;
@@ -398,10 +405,9 @@ k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc
             if (inc) {
                 const double dmax = d.lay.fixed_dpad ? (double)d.lay.fixed_dpad : (double)d.m;
                 const double gam = (dmax + 2.0) * 0x1p-52;
-                // each sum of m nonnegative terms is within (m + 4) 2^-52 of its exact value
-                const double up = 1.0 + ((double)d.m + 4.0) * 0x1p-52;
-                const double dlt = sqrt(dacc[3 * j] * up) * (1.0 + 0x1p-50);
-                const double rmax = sqrt(fmax(acc[4 * j], dacc[3 * j + 1]) * up) * (1.0 + 0x1p-50);
+                // |fl(x - o)| understates |x - o| by at most a relative 2^-53
+                const double dlt = dacc[4 * j] * (1.0 + 0x1p-50);
+                const double rmax = fmax(dacc[4 * j + 3], dacc[4 * j + 1]);
                 D = (dlt + 2.0 * gam * rmax) * (1.0 + 0x1p-40);
                 lo = (ist[4 * j] - ist[4 * j + 1] * D) * (1.0 - 0x1p-40) - 0x1p-1000;
             }

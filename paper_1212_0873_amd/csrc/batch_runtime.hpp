@@ -17,7 +17,7 @@ struct pcdm_batch {
 
     char *seg = nullptr;
     int64_t *pc_all = nullptr;
-    double *x = nullptr, *r64 = nullptr, *b = nullptr, *acc = nullptr;  // acc: 4 + 3 per problem
+    double *x = nullptr, *r64 = nullptr, *b = nullptr, *acc = nullptr;  // acc: 4 + 4 per problem
     // incremental ||A_j^T r_j||_inf: r of the last evaluation, per-column
     // upper bounds and norms (rounded up), per problem [M_old, max norm, -, valid]
     double *rold = nullptr, *ist = nullptr;
@@ -144,7 +144,7 @@ template <typename V> struct BatchOps {
         list(B, s, B->sel);
         refresh(B, s);
         double *dacc = B->acc + 4 * (int64_t)B->count;
-        hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, s, B->acc, 0.0, (int64_t)7 * B->count);
+        hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(kBlock), 0, s, B->acc, 0.0, (int64_t)8 * B->count);
         hipLaunchKernelGGL(k_batch_row_sums, dim3(grid_for(B->n_row_tiles * 64, kBlock, B->nblk_max)),
                            dim3(kBlock), 0, s, (const BatchInst *)B->desc, B->list, (const double *)B->b,
                            (const double *)B->r64, B->acc, B->rold, dacc);
@@ -156,14 +156,14 @@ template <typename V> struct BatchOps {
                            B->ist);
     }
 
-    // nrmc of problem j's columns (>= ||a_i||_2, float32 rounded up) and
+    // nrmc of problem j's columns (>= ||a_i||_1, float32 rounded up) and
     // ist[4j+1] = their maximum.
     static void col_norms(pcdm_batch *B, int j, double *part, hipStream_t s)
     {
         const BatchInst &d = B->hdesc[j];
         const double dmax = d.lay.fixed_dpad ? (double)d.lay.fixed_dpad : (double)d.m;
         const int g = grid_for(d.n, kBlock, B->nblk_max);
-        hipLaunchKernelGGL((k_col_norms<V>), dim3(g), dim3(kBlock), 0, s, (const char *)B->seg + d.rec_base, d.lay,
+        hipLaunchKernelGGL((k_col_norms<V, 8>), dim3(g), dim3(kBlock), 0, s, (const char *)B->seg + d.rec_base, d.lay,
                            d.n, 1.0 + (dmax + 8.0) * 0x1p-52, B->nrmc + d.col_base, part);
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, g, 1, 1, B->ist + 4 * j + 1);
     }
@@ -389,7 +389,7 @@ int batch_create_impl(int count, const pcdm_csc *A, const double *const *b, cons
     HIP_TRY(hipMalloc(&B->delta_slot, (size_t)slot_base * B->tbytes));
     HIP_TRY(hipMalloc(&B->desc, sizeof(BatchInst) * count));
     HIP_TRY(hipMalloc(&B->active, 4 * (size_t)count));
-    HIP_TRY(hipMalloc(&B->acc, 56 * (size_t)count));
+    HIP_TRY(hipMalloc(&B->acc, 64 * (size_t)count));
     HIP_TRY(hipMalloc(&B->rold, (size_t)row_base * 8));
     HIP_TRY(hipMemset(B->rold, 0, (size_t)row_base * 8));
     HIP_TRY(hipMalloc(&B->ubc, (size_t)col_base * 4));
@@ -552,7 +552,7 @@ int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream)
         B->hsel[j] = (!B->cvalid[j] || B->ck[j] != B->k_host[j]) ? 1 : 0;
         any = any || B->hsel[j];
     }
-    std::vector<double> acc(7 * (size_t)B->count, 0.0);
+    std::vector<double> acc(8 * (size_t)B->count, 0.0);
     if (any) {
         HIP_TRY(hipMemcpyAsync(B->sel, B->hsel.data(), 4 * (size_t)B->count, hipMemcpyHostToDevice, s));
         PCDM_TRY(batch_dispatch(B->dtype, [&](auto ops) {
@@ -560,7 +560,7 @@ int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream)
             return PCDM_OK;
         }));
         PCDM_TRY(check_launch("pcdm_batch_objective"));
-        HIP_TRY(hipMemcpyAsync(acc.data(), B->acc, 56 * (size_t)B->count, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(acc.data(), B->acc, 64 * (size_t)B->count, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
     for (int j = 0; j < B->count; ++j) {
@@ -573,7 +573,7 @@ int pcdm_batch_objective(pcdm_batch *B, double *F, double *gap, void *stream)
             B->cG[j] = Fj - (-0.5 * sc * sc * rr - sc * br);
             B->ck[j] = B->k_host[j];
             B->cvalid[j] = 1;
-            B->cands[j] = (int64_t)acc[4 * (size_t)B->count + 3 * j + 2];
+            B->cands[j] = (int64_t)acc[4 * (size_t)B->count + 4 * j + 2];
             if (B->incremental && B->inc_state[j])
                 B->inc_evals[j]++;
         }

@@ -1298,19 +1298,21 @@ k_atr_exact(const char *__restrict__ seg, Layout lay, const double *__restrict__
 // Incremental route between two evaluations of ||A^T r||_inf (float32 /
 // bf16 values).  Kept from the last evaluation: r_old (the r64 it used),
 // ub_i >= |a_i^T r_old| as the exact pass sums it, for every column, and its
-// result M_old.  For the new r64, Cauchy-Schwarz gives
-//     |a_i^T r_new| <= |a_i^T r_old| + ||a_i|| ||r_new - r_old||,
-// so with D = ||r_new - r_old|| + 2 gamma max(||r_old||, ||r_new||) (gamma =
-// (d_max + 2) 2^-52 covers the rounding of both exact sums) every column's
-// exact sum is at most ub_i + ||a_i|| D, and the new maximum is at least
-// M_old - max_i ||a_i|| D (the old maximiser moved by at most that).  Only
+// result M_old.  For the new r64, Hoelder's inequality gives
+//     |a_i^T r_new| <= |a_i^T r_old| + ||a_i||_1 ||r_new - r_old||_inf,
+// so with D = ||r_new - r_old||_inf + 2 gamma max(||r_old||_inf,
+// ||r_new||_inf) (gamma = (d_max + 2) 2^-52 covers the rounding of both exact
+// sums, each within gamma ||a_i||_1 ||r||_inf) every column's exact sum is at
+// most ub_i + ||a_i||_1 D, and the new maximum is at least
+// M_old - max_i ||a_i||_1 D (the old maximiser moved by at most that).  Only
 // the columns whose bound reaches that lower bound are summed exactly; the
-// bounds of the others grow by ||a_i|| D.  The result is the single pass's.
+// bounds of the others grow by ||a_i||_1 D.  The result is the single pass's.
 //
-// inc[0] = M_old, inc[1..3] = sum (r - r_old)^2, sum r^2, sum r_old^2,
+// inc[0] = M_old, inc[1..3] = max |r - r_old|, max |r|, max |r_old|,
 // inc[4] = D, inc[5] = the lower bound.
 
-// part[3 blk + {0, 1, 2}] = partial sums of (r - r_old)^2, r^2, r_old^2.
+// part[3 * blk + {0,1,2}] = the block's max |r - ro|, max |r|, max |ro|
+// (r: the float64 residual now, ro: the one of the last evaluation).
 __global__ void __launch_bounds__(kBlock)
 k_inc_sums(const double *__restrict__ r, const double *__restrict__ ro, int64_t m, double *__restrict__ part)
 {
@@ -1318,13 +1320,13 @@ k_inc_sums(const double *__restrict__ r, const double *__restrict__ ro, int64_t 
     double dd = 0.0, rr = 0.0, oo = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m; j += (int64_t)gridDim.x * kBlock) {
         const double a = r[j], o = ro[j];
-        dd += (a - o) * (a - o);
-        rr += a * a;
-        oo += o * o;
+        dd = fmax(dd, fabs(a - o));
+        rr = fmax(rr, fabs(a));
+        oo = fmax(oo, fabs(o));
     }
-    dd = block_sum_f64(dd, lds);
-    rr = block_sum_f64(rr, lds);
-    oo = block_sum_f64(oo, lds);
+    dd = block_max_f64(dd, lds);
+    rr = block_max_f64(rr, lds);
+    oo = block_max_f64(oo, lds);
     if (threadIdx.x == 0) {
         part[3 * blockIdx.x + 0] = dd;
         part[3 * blockIdx.x + 1] = rr;
@@ -1332,15 +1334,18 @@ k_inc_sums(const double *__restrict__ r, const double *__restrict__ ro, int64_t 
     }
 }
 
-// One thread: D and the lower bound from the sums (each sum of m terms is
-// within (m + 4) 2^-52 of its exact value, relative).
-__global__ void k_inc_prepare(double *__restrict__ inc, double nrm_max, double gam, double m)
+// One thread: D and the lower bound from the maxima.  The computed sum of
+// column i at r is within gam ||a_i||_1 ||r||_inf of a_i^T r (float64
+// summation of at most d products), and |a_i^T (r - ro)| <= ||a_i||_1
+// ||r - ro||_inf (Hoelder), so the computed sums move by at most
+// ||a_i||_1 D with D = ||r - ro||_inf + 2 gam max(||r||_inf, ||ro||_inf);
+// |fl(a - o)| understates |a - o| by at most a relative 2^-53.
+__global__ void k_inc_prepare(double *__restrict__ inc, double nrm_max, double gam)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
-    const double up = 1.0 + (m + 4.0) * 0x1p-52;
-    const double dlt = sqrt(inc[1] * up) * (1.0 + 0x1p-50);
-    const double rmax = sqrt(fmax(inc[2], inc[3]) * up) * (1.0 + 0x1p-50);
+    const double dlt = inc[1] * (1.0 + 0x1p-50);
+    const double rmax = fmax(inc[2], inc[3]);
     const double D = (dlt + 2.0 * gam * rmax) * (1.0 + 0x1p-40);
     inc[4] = D;
     inc[5] = (inc[0] - nrm_max * D) * (1.0 - 0x1p-40) - 0x1p-1000;
@@ -1426,24 +1431,41 @@ k_atr_inc(const char *__restrict__ seg, Layout lay, const double *__restrict__ r
         part[blockIdx.x] = best;
 }
 
-// nrm_i >= ||a_i||_2 (float32, rounded up) from the header's 1/L_i, with the
-// relative margin `fac` for the rounding of L_i; part[blk] = the block's max.
-template <typename V>
+// nrm_i >= ||a_i||_1 (float32, rounded up; `fac` covers the float64
+// summation), part[blk] = the block's max.
+template <typename V, int G>
 __global__ void __launch_bounds__(kBlock)
 k_col_norms(const char *__restrict__ seg, Layout lay, int64_t n, double fac, float *__restrict__ nrm,
             double *__restrict__ part)
 {
+    using T = typename ValT<V>::T;
     __shared__ double lds[kBlock];
+    const TileLanes<G> tl;
     double best = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        int64_t off;
-        int32_t dp;
-        locate<V>(lay, i, off, dp);
-        const double il = reinterpret_cast<const double *>(seg + off)[1];
-        const double v = sqrt(1.0 / il) * fac;
-        const float u = round_up_f32(v);
-        nrm[i] = u;
-        best = fmax(best, (double)u);
+    for (int64_t base = wave_global_id() * 64; base < n; base += wave_count() * 64) {
+        const int64_t col = base + tl.lane;
+        int64_t off = 0;
+        int32_t dp = 0;
+        if (col < n)
+            locate<V>(lay, col, off, dp);
+        double acc[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            acc[q] = 0.0;
+        tile_entries<V, G>(seg, tl, off, dp, 0, [&](int q, int, int, T val) { acc[q] += fabs((double)val); });
+        double mine = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const double s = group_sum<G>(acc[q]);
+            const double got = __shfl(s, tl.leader_of_mine(q));
+            if (tl.lane / TileLanes<G>::CPR == q)
+                mine = got;
+        }
+        if (col < n) {
+            const float u = round_up_f32(mine * fac);
+            nrm[col] = u;
+            best = fmax(best, (double)u);
+        }
     }
     best = block_max_f64(best, lds);
     if (threadIdx.x == 0)

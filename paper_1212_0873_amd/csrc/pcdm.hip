@@ -127,8 +127,8 @@ struct pcdm_problem {
     int max_passes = 0;       // ||A^T r||_inf: 2 = bound + exact pass where available, 1 = one exact pass,
                               // 3 = incremental from the last evaluation where it pays, else as 2,
                               // 0 = 3 from kIncMinEntries stored entries, else 2
-    // incremental route: r of the last evaluation, column norms (rounded up),
-    // [M_old, sums, D, lower bound], candidate count; valid after a 2- or 3-route evaluation
+    // incremental route: r of the last evaluation, column l1 norms (rounded up),
+    // [M_old, maxima, D, lower bound], candidate count; valid after a 2- or 3-route evaluation
     double *rold = nullptr;
     float *nrm = nullptr;
     double *inc = nullptr;
@@ -722,8 +722,8 @@ template <typename V> struct Ops {
             // bounds moved from the last evaluation; taken when few columns remain
             const int gm = grid_for(P->m, kBlock, kReduceBlocks);
             hipLaunchKernelGGL(k_inc_sums, dim3(gm), dim3(kBlock), 0, s, rv, (const double *)P->rold, P->m, P->part);
-            hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part, gm, 3, 0, P->inc + 1);
-            hipLaunchKernelGGL(k_inc_prepare, dim3(1), dim3(1), 0, s, P->inc, P->nrm_max, P->gam, (double)P->m);
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part, gm, 3, 1, P->inc + 1);
+            hipLaunchKernelGGL(k_inc_prepare, dim3(1), dim3(1), 0, s, P->inc, P->nrm_max, P->gam);
             hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(kBlock), 0, s, P->cnt, 0ull, (int64_t)1);
             hipLaunchKernelGGL(k_inc_count, dim3(grid), dim3(kBlock), 0, s, (const float *)P->ub,
                                (const float *)P->nrm, P->n, (const double *)P->inc, P->cnt);
@@ -778,12 +778,12 @@ template <typename V> struct Ops {
         P->inc_valid = true;
     }
 
-    // Column norms for the incremental route (rounded up) and their maximum.
+    // Column l1 norms for the incremental route (rounded up) and their maximum.
     static int col_norms(pcdm_problem *P, hipStream_t s)
     {
         const int grid = grid_for(P->n, kBlock, P->nblk_max);
         const double dmax = P->lay.fixed_dpad ? (double)P->lay.fixed_dpad : (double)P->m;
-        hipLaunchKernelGGL((k_col_norms<V>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, P->n,
+        hipLaunchKernelGGL((k_col_norms<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, P->n,
                            1.0 + (dmax + 8.0) * 0x1p-52, P->nrm, P->part2);
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
                            P->ctrl->scal + 5);
