@@ -31,7 +31,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -39,6 +39,8 @@ def build(force: bool = False) -> str:
 _I64P = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _F64P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_F32P = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_I32MP = np.ctypeslib.ndpointer(dtype=np.int32, flags=("C_CONTIGUOUS", "WRITEABLE"))
 _i64 = ctypes.c_int64
 _u64 = ctypes.c_uint64
 _f64 = ctypes.c_double
@@ -88,6 +90,8 @@ def _lib():
                                                    _F64P]),
                 "orc_model_run": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _F64P, ctypes.c_int, _f64, _f64,
                                          _f64, _f64, _f64, _f64, _f64, _i64, _u64, _i64, _i64, _F64P, _F64P]),
+                "orc_column_stats_f32": (ctypes.c_int, [_i64, _I64P, _I32P, _F32P, _F64P, _i64, _I32MP,
+                                                        ctypes.POINTER(_f64), ctypes.c_int]),
                 "orc_pcdm_run_sampling": (_i64, [_i64, _i64, _I64P, _I32P, _F64P, _F64P, _f64, _f64,
                                                  _i64, _u64, _i64, _i64, ctypes.c_int, _f64,
                                                  ctypes.c_void_p, _i64, _F64P, _F64P]),
@@ -459,3 +463,105 @@ class ModelSolver:
 
     def steps_per_epoch(self) -> int:
         return -(-self.n // self.tau)
+
+
+# --------------------------------------------------------------------------- #
+# instances too large to hold on the host as float64
+# --------------------------------------------------------------------------- #
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+class ColumnStats:
+    """omega = max_j #{i : a_ji != 0} and ||A^T b||_inf of a matrix streamed
+    in column slices with float32 stored values (introduction, partial
+    separability; the lambda rule of the LASSO experiments).  Each slice is
+    split over threads; the counts and the maximum equal those of one serial
+    pass over the whole matrix."""
+
+    def __init__(self, m: int, b):
+        self.m = int(m)
+        self.b = np.ascontiguousarray(b, dtype=np.float64)
+        if self.b.size != self.m:
+            raise ValueError("b has the wrong length")
+        self.counts = np.zeros(self.m, dtype=np.int32)
+        self.atb_inf = 0.0
+        self.ncols = 0
+
+    def add(self, col_ptr, row_idx, val_f32) -> None:
+        """Columns whose entries are row_idx/val_f32[col_ptr[i] - col_ptr[0] ..]."""
+        cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+        cp = cp - cp[0]
+        ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+        v = np.ascontiguousarray(val_f32, dtype=np.float32)
+        if ri.size < cp[-1] or v.size < cp[-1]:
+            raise ValueError("slice shorter than its column pointers")
+        best = _f64()
+        if _lib().orc_column_stats_f32(cp.size - 1, cp, ri, v, self.b, self.m, self.counts, ctypes.byref(best),
+                                       _threads()) != 0:
+            raise ValueError("row index out of range")
+        self.atb_inf = max(self.atb_inf, best.value)
+        self.ncols += cp.size - 1
+
+    @property
+    def omega(self) -> int:
+        return int(self.counts.max()) if self.m else 0
+
+
+class ColumnSetSolver:
+    """Synchronous PCDM1 state for an instance whose columns do not fit on the
+    host: x (float64 [n]) and r = A x - b (float64 [m], r = -b at x = 0) are
+    held whole, and each step receives the columns of its set S_k from the
+    caller (stored values, widened exactly).  The step is Algorithm PCDM1's,
+    through the same C step as ``Solver`` (every g_i from r_k, then the
+    updates in ascending coordinate order); lambda and beta are the caller's."""
+
+    def __init__(self, m: int, n: int, b, lam: float, beta: float):
+        self.m, self.n = int(m), int(n)
+        self.lam, self.beta = float(lam), float(beta)
+        self.r = -np.ascontiguousarray(b, dtype=np.float64)
+        if self.r.size != self.m:
+            raise ValueError("b has the wrong length")
+        self.x = np.zeros(self.n)
+        self.changed = 0
+
+    @staticmethod
+    def _sub(S, col_ptr, row_idx, val):
+        S = np.ascontiguousarray(S, dtype=np.int64)
+        if S.size > 1 and np.any(np.diff(S) <= 0):
+            raise ValueError("S must be ascending and distinct")
+        cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+        cp = cp - cp[0]
+        if cp.size != S.size + 1:
+            raise ValueError("one column per element of S")
+        ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        return S, cp, ri, v
+
+    def gradient(self, S, col_ptr, row_idx, val) -> np.ndarray:
+        """g_i = a_i^T r at the current r for the given columns of S."""
+        S, cp, ri, v = self._sub(S, col_ptr, row_idx, val)
+        g = np.empty(S.size)
+        _lib().orc_gradient(S.size, cp, ri, v, self.r, g)
+        return g
+
+    def step_with_columns(self, S, col_ptr, row_idx, val) -> int:
+        """One step on the set S (ascending) whose columns are given in S's
+        order; returns the number of coordinates that changed."""
+        S, cp, ri, v = self._sub(S, col_ptr, row_idx, val)
+        L = np.empty(S.size)
+        _lib().orc_lipschitz(S.size, cp, v, L)
+        xs = np.ascontiguousarray(self.x[S])
+        local = np.arange(S.size, dtype=np.int64)
+        c = _lib().orc_step_with_set(self.m, S.size, cp, ri, v, L, self.lam, self.beta, S.size, local, xs,
+                                     self.r)
+        if c < 0:
+            raise ValueError("bad set")
+        self.x[S] = xs
+        self.changed += int(c)
+        return int(c)
+
+    def objective(self) -> float:
+        """F(x) = 0.5*||r||^2 + lambda*||x||_1 on the maintained r."""
+        return _lib().orc_objective(self.m, self.n, self.r, self.x, self.lam)

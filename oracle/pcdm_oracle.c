@@ -38,6 +38,7 @@
  * ascending coordinate index.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -99,6 +100,94 @@ void orc_lipschitz(int64_t n, const int64_t *col_ptr, const double *val, double 
             s += val[p] * val[p];
         L[i] = s;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* omega and ||A^T b||_inf of a matrix too large to hold as float64.         */
+/*                                                                           */
+/* The caller streams A in column slices with the stored float32 values     */
+/* (widened exactly); each call adds the slice's nonzeros to per-row counts */
+/* (omega is the largest count once every slice is in) and returns the      */
+/* largest |a_i^T b| of the slice (the lambda rule of the experiments is a  */
+/* multiple of ||A^T b||_inf).  Columns are split over threads: a row count */
+/* is a sum of increments and a maximum does not depend on the order, so    */
+/* the results equal those of one serial pass.  Each a_i^T b is summed in   */
+/* ascending entry order in float64.                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t c0, c1;
+    const int64_t *col_ptr;
+    const int32_t *row_idx;
+    const float *val;
+    const double *b;
+    int64_t m;
+    int32_t *counts;
+    double best;
+    int bad;
+} orc_stats_job;
+
+static void *orc_stats_worker(void *arg)
+{
+    orc_stats_job *J = (orc_stats_job *)arg;
+    for (int64_t i = J->c0; i < J->c1; ++i) {
+        double s = 0.0;
+        for (int64_t p = J->col_ptr[i]; p < J->col_ptr[i + 1]; ++p) {
+            const int32_t row = J->row_idx[p];
+            if (row < 0 || (int64_t)row >= J->m) {
+                J->bad = 1;
+                return NULL;
+            }
+            s += (double)J->val[p] * J->b[row];
+            if (J->val[p] != 0.0f)
+                __atomic_fetch_add(&J->counts[row], 1, __ATOMIC_RELAXED);
+        }
+        if (fabs(s) > J->best)
+            J->best = fabs(s);
+    }
+    return NULL;
+}
+
+/* Slice of ncols columns: entries col_ptr[i] .. col_ptr[i+1]-1 of row_idx and
+ * val belong to the slice's column i.  counts[m] accumulates; *absdot_max
+ * receives the slice's largest |a_i^T b|.  A thread that cannot be started
+ * has its share run on the calling thread.  Returns 0, or -1 on a row out of
+ * range. */
+int orc_column_stats_f32(int64_t ncols, const int64_t *col_ptr, const int32_t *row_idx, const float *val,
+                         const double *b, int64_t m, int32_t *counts, double *absdot_max, int nthreads)
+{
+    orc_stats_job jobs[64];
+    pthread_t th[64];
+    int started[64];
+    int nt = nthreads < 1 ? 1 : (nthreads > 64 ? 64 : nthreads);
+    double best = 0.0;
+    int bad = 0;
+    if (ncols < 0)
+        return -1;
+    for (int t = 0; t < nt; ++t) {
+        jobs[t].c0 = ncols * t / nt;
+        jobs[t].c1 = ncols * (t + 1) / nt;
+        jobs[t].col_ptr = col_ptr;
+        jobs[t].row_idx = row_idx;
+        jobs[t].val = val;
+        jobs[t].b = b;
+        jobs[t].m = m;
+        jobs[t].counts = counts;
+        jobs[t].best = 0.0;
+        jobs[t].bad = 0;
+        started[t] = pthread_create(&th[t], NULL, orc_stats_worker, &jobs[t]) == 0;
+        if (!started[t])
+            orc_stats_worker(&jobs[t]);
+    }
+    for (int t = 0; t < nt; ++t) {
+        if (started[t])
+            pthread_join(th[t], NULL);
+        bad |= jobs[t].bad;
+        if (jobs[t].best > best)
+            best = jobs[t].best;
+    }
+    *absdot_max = best;
+    return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------------ */
