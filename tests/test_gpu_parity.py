@@ -362,9 +362,27 @@ def test_full_size_steps_match_oracle(pc, c2_full):
         info = p.info()
         _say(f"omega {info['omega']} beta {info['beta']:.4f} lanes {info['lanes_per_column']}")
         assert info["omega"] == ref.omega
+        # step 0 starts at x = 0: coordinate i changes iff |g_i| > lambda with
+        # g_i = a_i^T r = -a_i^T b.  The device sums d float32 products of
+        # fl32(-b), within (d + 3) 2^-24 sum_j |a_ji||b_j| of g_i; only
+        # coordinates with |g_i| that close to lambda may count differently.
+        S0 = oracle.sample_nice(0, 0, tau, inst.A.n).astype(np.int64)
+        d = int(inst.A.col_ptr[1] - inst.A.col_ptr[0])
+        assert np.all(np.diff(inst.A.col_ptr) == d)
+        idx = inst.A.col_ptr[S0][:, None] + np.arange(d)
+        av = inst.A.values_f64()[idx]
+        bv = inst.b[inst.A.row_idx[idx]]
+        g0 = -(av * bv).sum(axis=1)
+        bound = (d + 3) * 2.0 ** -24 * (np.abs(av) * np.abs(bv)).sum(axis=1)
+        edge = int(np.count_nonzero(np.abs(np.abs(g0) - inst.lam) <= bound))
         for s in range(3):
             p.step(1)
             ref.step(1)
+            if s == 0:
+                got = p.info()["nonzero_updates"]
+                _say(f"step 1: nonzero updates gpu {got} oracle {ref.changed} ({edge} at the threshold)")
+                assert ref.changed == int(np.count_nonzero(np.abs(g0) > inst.lam)) or edge > 0
+                assert abs(got - ref.changed) <= edge
             F, _ = p.objective()
             Fr = ref.objective()
             _say(f"step {s + 1}: F {F:.9e} oracle {Fr:.9e}")
@@ -373,7 +391,7 @@ def test_full_size_steps_match_oracle(pc, c2_full):
         scale = np.max(np.abs(ref.x))
         assert np.max(np.abs(x - ref.x)) <= 1e-5 * scale
         assert np.array_equal(x != 0, ref.x != 0) or np.mean((x != 0) != (ref.x != 0)) < 1e-5
-        _say(f"nonzero updates gpu {p.info()['nonzero_updates']} oracle {ref.changed}")
+        _say(f"nonzero updates after 3 steps: gpu {p.info()['nonzero_updates']} oracle {ref.changed}")
 
 
 # --------------------------------------------------------------------------- #

@@ -32,7 +32,7 @@ def build() -> None:
                            os.path.join(CSRC, "gen_device.hip"), "-o", tmp])
     os.replace(tmp, DEV_LIB)
     tmp = HOST_LIB + f".tmp{os.getpid()}"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-I", CSRC,
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-I", CSRC,
                            os.path.join(CSRC, "gen_host.c"), "-o", tmp, "-lm"])
     os.replace(tmp, HOST_LIB)
 
@@ -52,6 +52,13 @@ def _host_lib():
         lib.gen_host_noise_rows.restype = None
         lib.gen_host_csc.argtypes = [u64, u64, u64, i32, i32, vp, vp]
         lib.gen_host_csc.restype = i32
+        i64 = ctypes.c_int64
+        lib.gen_host_columns.argtypes = [u64, u64, u64, i32, i32, u64, i64, vp, vp, vp, i32]
+        lib.gen_host_columns.restype = i32
+        lib.gen_host_column_list.argtypes = [u64, u64, u64, i32, i32, vp, i64, vp, vp, vp, i32]
+        lib.gen_host_column_list.restype = i32
+        lib.gen_host_b.argtypes = [u64, u64, u64, i32, u64, f64, i32, vp, i32]
+        lib.gen_host_b.restype = i32
         _host = lib
     return _host
 
@@ -106,6 +113,52 @@ def host_b_at(seed: int, m: int, n: int, d: int, K: int, sigma: float, rows, dty
     noise = np.empty(rows.size, dtype=np.float64)
     _host_lib().gen_host_noise_rows(seed, rows.ctypes.data, rows.size, float(sigma), noise.ctypes.data)
     return ax[rows] + noise
+
+
+def host_threads() -> int:
+    """Worker threads for the host regeneration: the CPUs this process may
+    use, at most 16."""
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        cpus = os.cpu_count() or 1
+    return max(1, min(16, cpus))
+
+
+def host_columns(seed: int, m: int, n: int, d: int, i0: int, count: int, dtype: str = "f32",
+                 threads: int | None = None):
+    """Columns [i0, i0 + count) of the recipe: (col_ptr relative to i0, rows
+    int32, stored values as float32).  For f32 / bf16 storage."""
+    if dtype == "f64":
+        raise ValueError("float32 output holds f32 and bf16 stored values only")
+    rows = np.empty(count * d, dtype=np.int32)
+    vals = np.empty(count * d, dtype=np.float32)
+    if _host_lib().gen_host_columns(seed, m, n, d, DTYPE_CODE[dtype], i0, count, rows.ctypes.data,
+                                    vals.ctypes.data, None, threads or host_threads()) != 0:
+        raise ValueError("bad column range")
+    return np.arange(count + 1, dtype=np.int64) * d, rows, vals
+
+
+def host_column_list(seed: int, m: int, n: int, d: int, cols, dtype: str = "f32", threads: int | None = None):
+    """The given columns (in the given order): (col_ptr, rows int32, stored
+    values as float64)."""
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    rows = np.empty(cols.size * d, dtype=np.int32)
+    vals = np.empty(cols.size * d, dtype=np.float64)
+    if _host_lib().gen_host_column_list(seed, m, n, d, DTYPE_CODE[dtype], cols.ctypes.data, cols.size,
+                                        rows.ctypes.data, None, vals.ctypes.data, threads or host_threads()) != 0:
+        raise ValueError("bad column list")
+    return np.arange(cols.size + 1, dtype=np.int64) * d, rows, vals
+
+
+def host_b(seed: int, m: int, n: int, d: int, K: int, sigma: float, dtype: str = "f32",
+           threads: int | None = None):
+    """All of b (float64 [m]) = A x* (stored values) + noise."""
+    b = np.empty(m, dtype=np.float64)
+    if _host_lib().gen_host_b(seed, m, n, d, K, float(sigma), DTYPE_CODE[dtype], b.ctypes.data,
+                              threads or host_threads()) != 0:
+        raise ValueError("bad instance request")
+    return b
 
 
 def host_instance(m: int, n: int, d: int, K: int, sigma: float, seed: int = 0, dtype: str = "f32"):
