@@ -377,6 +377,27 @@ int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db,
                        double *dL_dlambda, int32_t on_device, void *stream);
 
 /*
+ * pcdm_grad_backward for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: tight serving loops, harnesses that forbid
+ * allocation): the same solve and kernels, with every temporary carved from
+ * a fixed 32 MiB device region that the library holds for the life of the
+ * process, one copy per device (looked up on the first call on a device).
+ * No hipMalloc, hipFree or allocating library routine is called.
+ *   dL_dx [n], dL_db [m]: device pointers (float64); dL_dlambda: host scalar.
+ * The handle's device must be current.  The temporaries need about
+ * 13 n + 12 m + 16 |S| + 12 tau_S bytes (each piece rounded up to 256 bytes,
+ * plus the stream compaction's work space); a problem that needs more than
+ * 32 MiB is rejected with PCDM_EINVAL before the solve starts (use
+ * pcdm_grad_backward).  Every call on one device shares the one region and
+ * leaves its contents behind (each call fills what it reads before reading
+ * it): calls that overlap in time on one device, from any handles or
+ * threads, race and must be serialised by the caller.  Results as
+ * pcdm_grad_backward; synchronous.
+ */
+int pcdm_grad_backward_noalloc(pcdm_problem *h, const double *dL_dx, double *dL_db,
+                               double *dL_dlambda, void *stream);
+
+/*
  * Replace b (m float64 values, host or device) and recompute r = A x - b in
  * float64 and ||A^T b||_inf (pcdm_info.atb_inf).  x and k are kept (warm
  * start).  Synchronous.

@@ -17,7 +17,8 @@ STATUS_NAMES = {0: "PCDM_OK", -1: "PCDM_EINVAL", -2: "PCDM_ENOMEM", -3: "PCDM_ED
 # every symbol include/pcdm.h declares
 EXPORTS = ("pcdm_create", "pcdm_destroy", "pcdm_last_error", "pcdm_set_option", "pcdm_get_info",
            "pcdm_step", "pcdm_objective", "pcdm_get_x", "pcdm_set_x", "pcdm_get_residual",
-           "pcdm_grad_backward", "pcdm_set_rhs", "pcdm_kernel_time", "pcdm_autotune", "pcdm_sample",
+           "pcdm_grad_backward", "pcdm_grad_backward_noalloc", "pcdm_set_rhs", "pcdm_kernel_time",
+           "pcdm_autotune", "pcdm_sample",
            "pcdm_sample_draw", "pcdm_set_slot_mask", "pcdm_step_async", "pcdm_create_model",
            "pcdm_create_group",
            "pcdm_batch_create", "pcdm_batch_step", "pcdm_batch_objective", "pcdm_batch_set_active",
@@ -92,6 +93,7 @@ def load() -> ctypes.CDLL:
             "pcdm_set_x": [vp, vp, i32, i32, i64, vp],
             "pcdm_get_residual": [vp, vp, i32, vp],
             "pcdm_grad_backward": [vp, vp, vp, pd, i32, vp],
+            "pcdm_grad_backward_noalloc": [vp, vp, vp, pd, vp],
             "pcdm_sample": [u64, u64, i64, i64, vp, vp],
             "pcdm_sample_draw": [i32, f64, u64, u64, i64, i64, vp, vp],
             "pcdm_set_slot_mask": [vp, vp, i64, i32, vp],

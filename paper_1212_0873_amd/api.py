@@ -236,6 +236,21 @@ class Problem:
                                                current_stream()))
         return out, dl.value
 
+    def grad_backward_noalloc(self, dL_dx, out=None):
+        """grad_backward through ``pcdm_grad_backward_noalloc``: dL_dx a CUDA
+        tensor, dL/db written into ``out`` (a float64 CUDA tensor of m, or a
+        new one) with no device allocation inside the library."""
+        torch = _torch()
+        g = dL_dx if dL_dx.dtype == torch.float64 and dL_dx.is_contiguous() else dL_dx.to(torch.float64).contiguous()
+        if out is None:
+            out = torch.empty(self.m, dtype=torch.float64, device=g.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != self.m:
+            raise ValueError("out must be a contiguous float64 tensor of m entries")
+        dl = ctypes.c_double()
+        check(self._lib.pcdm_grad_backward_noalloc(self._h, g.data_ptr(), out.data_ptr(), ctypes.byref(dl),
+                                                   current_stream()))
+        return out, dl.value
+
     def set_rhs(self, b) -> None:
         """Replace b (warm start: x and k are kept)."""
         if isinstance(b, np.ndarray):

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -22,6 +23,14 @@
 #include "pcdm.h"
 
 using namespace pcdm;
+
+// Fixed device region for the entry points that allocate nothing
+// (pcdm_grad_backward_noalloc).  Each device the library runs on holds its
+// own copy until the process ends.  Host code never passes `scratch` itself
+// to a kernel or a copy: that name is the host-side stand-in; the device
+// address comes from hipGetSymbolAddress (scratch_base).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -872,6 +881,25 @@ int check_launch(const char *what)
     return PCDM_OK;
 }
 
+// Device address of `scratch` on device `dev`, looked up once per device
+// (with that device current) and kept.
+int scratch_base(int dev, void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(PCDM_EDEVICE, "device ordinal out of range for the fixed scratch");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return PCDM_OK;
+}
+
 // Device temporaries of one call, freed when it returns.
 struct DevTemps {
     std::vector<void *> p;
@@ -889,6 +917,29 @@ struct DevTemps {
             return hip_fail(e, "temporary allocation");
         p.push_back(q);
         *out = (T *)q;
+        return PCDM_OK;
+    }
+};
+
+// Where one call's device temporaries come from: hipMalloc through a
+// DevTemps (freed when the call returns), or consecutive 256-byte aligned
+// pieces of a fixed device region that is never freed (no allocation at all).
+struct TempSource {
+    DevTemps *heap = nullptr;
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    const char *who = "";
+    template <typename T> int get(T **out, size_t bytes)
+    {
+        if (heap)
+            return heap->get(out, bytes);
+        const size_t need = (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+        if (used + need > cap)
+            return fail(PCDM_EINVAL, std::string(who) + ": needs more than the fixed scratch of " +
+                                         std::to_string(cap) + " bytes (" + std::to_string(used + need) +
+                                         " bytes taken so far); call the allocating entry point instead");
+        *out = (T *)(base + used);
+        used += need;
         return PCDM_OK;
     }
 };
@@ -1722,17 +1773,16 @@ int pcdm_get_residual(pcdm_problem *h, double *r_out, int32_t on_device, void *s
     return st;
 }
 
-int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db, double *dL_dlambda,
-                       int32_t on_device, void *stream)
+// The adjoint solve of pcdm_grad_backward with its temporaries from `tmp`.
+static int grad_backward_impl(pcdm_problem *h, const double *dL_dx, double *dL_db, double *dL_dlambda,
+                              int32_t on_device, hipStream_t s, TempSource &tmp)
 {
     if (!h || !dL_dx || !dL_db || !dL_dlambda)
         return fail(PCDM_EINVAL, "NULL argument");
     if (!is_lasso(h))
         return fail(PCDM_EINVAL, "the adjoint is built for the LASSO (square loss, l1 term)");
-    hipStream_t s = (hipStream_t)stream;
     h->last_stream = s;
     const int64_t n = h->n, m = h->m;
-    DevTemps tmp;  // freed on every exit
     double *g = nullptr, *gS = nullptr, *vS = nullptr, *rho = nullptr, *dels = nullptr;
     uint8_t *flags = nullptr;
     int32_t *S = nullptr, *ids = nullptr, *hist = nullptr, *nsel = nullptr;
@@ -1839,6 +1889,35 @@ int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db, doub
                                        std::to_string(h->adj_last_resid) + " after " + std::to_string(epoch) +
                                        " epochs");
     return PCDM_OK;
+}
+
+int pcdm_grad_backward(pcdm_problem *h, const double *dL_dx, double *dL_db, double *dL_dlambda,
+                       int32_t on_device, void *stream)
+{
+    DevTemps heap;  // freed on every exit
+    TempSource tmp;
+    tmp.heap = &heap;
+    return grad_backward_impl(h, dL_dx, dL_db, dL_dlambda, on_device, (hipStream_t)stream, tmp);
+}
+
+int pcdm_grad_backward_noalloc(pcdm_problem *h, const double *dL_dx, double *dL_db, double *dL_dlambda,
+                               void *stream)
+{
+    if (!h || !dL_dx || !dL_db || !dL_dlambda)
+        return fail(PCDM_EINVAL, "NULL argument");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device)
+        return fail(PCDM_EINVAL, "pcdm_grad_backward_noalloc: the handle was created on device " +
+                                     std::to_string(h->device) + " but device " + std::to_string(dev) +
+                                     " is current");
+    void *base = nullptr;
+    PCDM_TRY(scratch_base(dev, &base));
+    TempSource tmp;
+    tmp.base = (char *)base;
+    tmp.cap = kScratchBytes;
+    tmp.who = "pcdm_grad_backward_noalloc";
+    return grad_backward_impl(h, dL_dx, dL_db, dL_dlambda, 1, (hipStream_t)stream, tmp);
 }
 
 int pcdm_set_rhs(pcdm_problem *h, const double *b, int32_t on_device, void *stream)
