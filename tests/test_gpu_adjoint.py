@@ -150,3 +150,32 @@ def test_full_size_adjoint_finite_differences(pc):
         fd = (L_at(inst.b, inst.lam + h) - L_at(inst.b, inst.lam - h)) / (2 * h)
         _say(f"lambda: fd {fd:.8e} adjoint {dl:.8e}")
         assert fd == pytest.approx(dl, rel=1e-3)
+
+
+def test_full_size_float32_adjoint_matches_oracle(pc):
+    """1e5 x 1e6 training matrix with float32 values: the float32 forward
+    solve (float32 A and r, float64 refresh and x) to a certified 1e-7 gap,
+    then dL/db and dL/dlambda of the validation loss through the library's
+    adjoint, against the oracle's float64 support solve at the oracle's own
+    solution on the same stored values (same support and signs)."""
+    import time
+    inst = make_config("train_1e5x1e6", dtype="f32", tau=4096)
+    rng = np.random.default_rng(3)
+    V = _sparse(random_csc(20000, inst.A.n, 10, rng, normalize=False))
+    loss = _val_loss_grad(V, inst.xstar)
+    t0 = time.time()
+    x_ref = _oracle_solution(inst, tau=4096, tol=1e-11)
+    want_db, want_dl = oracle.lasso_adjoint(inst.A, x_ref, loss(x_ref)[1])
+    _say(f"oracle: support {np.count_nonzero(x_ref)} ({time.time() - t0:.0f} s)")
+    with pc.Problem(inst.A, inst.b, inst.lam, 4096, seed=2) as p:
+        p.set_option("adj_tol", 1e-9)
+        st = p.solve(rel_gap=1e-7, check_every=5, max_epochs=4000)
+        _say(f"forward: {st}")
+        assert st["converged"], st
+        x = p.get_x()
+        got_db, got_dl = p.grad_backward(loss(x)[1])
+    assert np.array_equal(np.sign(x), np.sign(x_ref))
+    err = np.max(np.abs(got_db - want_db)) / np.max(np.abs(want_db))
+    _say(f"dL/db rel err {err:.2e}; dL/dlambda {got_dl:.9e} vs {want_dl:.9e}")
+    assert err <= 1e-4
+    assert got_dl == pytest.approx(want_dl, rel=1e-4)

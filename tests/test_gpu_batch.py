@@ -142,3 +142,50 @@ def test_batch_gap_incremental_max(pc, dtype):
             assert all(B1.info(j)["max_incremental"] == 0 for j in range(len(probs)))
             assert all(B1.info(j)["max_candidates"] == A.n for j, (A, _, _, _) in enumerate(probs))
         np.testing.assert_allclose(gap1, gap, rtol=1e-7, atol=1e-12 * np.abs(F).max())
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f64", 1e-10)])
+def test_batched_path_shape_matches_oracle(pc, dtype, tol):
+    """The batched regularisation-path workload at its real shape: 64
+    problems with n_j log-uniform on [1e3, 1e6] (m_j = n_j/5, 10 entries per
+    column), lambda_j on the geometric grid, tau_j = min(n_j, 4096), one
+    batch.  Every problem against the oracle run alone with the batch's key
+    (seed + j) for 490 steps (two epochs of the largest problem; hundreds of
+    the smallest), F at five checks; float64 values also x; at the end every
+    certified gap against scipy's at the batch's own x."""
+    import time
+
+    from workloads.configs import batched_path
+    t0 = time.time()
+    insts = batched_path(64, seed=0, dtype=dtype)
+    probs = [(i.A, i.b, i.lam, min(i.A.n, 4096)) for i in insts]
+    ns = [A.n for A, _, _, _ in probs]
+    _say(f"{dtype}: 64 problems, n {min(ns)} .. {max(ns)}, sum n {sum(ns)} ({time.time() - t0:.0f} s)")
+    refs = [oracle.Solver(A, b, lam, tau=tau, seed=11 + j) for j, (A, b, lam, tau) in enumerate(probs)]
+    with pc.Batch(probs, seed=11) as B:
+        for j, r in enumerate(refs):
+            inf = B.info(j)
+            assert inf["omega"] == r.omega and inf["beta"] == pytest.approx(r.beta, rel=1e-15), j
+        for rnd in range(5):
+            steps = 98
+            B.step(steps)
+            for r in refs:
+                r.step(steps)
+            F, gap = B.objective()
+            worst = 0.0
+            for j, r in enumerate(refs):
+                Fr = r.objective()
+                worst = max(worst, abs(F[j] - Fr) / abs(Fr))
+                assert F[j] == pytest.approx(Fr, rel=tol), (rnd, j)
+            _say(f"  check {rnd}: worst rel F error {worst:.2e} ({time.time() - t0:.0f} s)")
+        if dtype == "f64":
+            for j, r in enumerate(refs):
+                np.testing.assert_allclose(B.get_x(j), r.x, atol=1e-9, err_msg=str(j))
+        for j, (A, b, lam, tau) in enumerate(probs):
+            g_ref, _ = _scipy_gap(A, b, B.get_x(j), lam)
+            assert gap[j] == pytest.approx(g_ref, rel=1e-6, abs=1e-10 * abs(F[j])), j
+        assert all(B.info(j)["k"] == 490 for j in range(64))
+
+
+def _say(msg):
+    print(msg, flush=True)
