@@ -766,6 +766,69 @@ def run_adjoint(args) -> int:
     return 0
 
 
+def steps_to_eps(p, Fstar: float, F0: float, eps: float, chunk: int, limit: int) -> int:
+    """PCDM steps until F(x_k) - F* <= eps (F(x_0) - F*), checked every
+    `chunk` steps (the count is exact to within one chunk); -1 if `limit`
+    steps do not get there."""
+    steps = 0
+    while steps < limit:
+        p.step(chunk)
+        steps += chunk
+        F, _ = p.objective()
+        if F - Fstar <= eps * (F0 - Fstar):
+            return steps
+    return -1
+
+
+def run_theory(args) -> int:
+    """'Theory versus reality': 0.5||Ax - b||^2 (lambda = 0) with A 3000 x 1000
+    holding exactly omega equal nonzeros (ones) in every row and 3 omega in
+    every column (random pattern), b ~ N(0, 1), for omega in {5, 10, 50, 100}
+    and tau from 1 to 1000.  Steps of PCDM1 with tau-nice sampling until
+    F(x_k) - F* <= 1e-6 (F(x_0) - F*), F* from a dense float64 least-squares
+    solve; the empirical speedup (steps at tau = 1) / (steps at tau) beside the
+    theoretical factor tau / beta.  The paper shows this only as a figure, so
+    it is a report (no gate)."""
+    import numpy as np
+    import scipy.linalg
+    import torch
+
+    import paper_1212_0873_amd as pc
+    from workloads import biregular_matrix, csc_to_dense
+
+    torch.cuda.set_device(0)
+    n, m, eps = 1000, 3000, 1e-6
+    taus = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1000]
+    rows = []
+    t0 = time.perf_counter()
+    for omega in (5, 10, 50, 100):
+        A = biregular_matrix(m, n, omega, np.random.default_rng(omega))
+        b = np.random.default_rng(1000 + omega).standard_normal(m)
+        M = csc_to_dense(A)
+        xs = scipy.linalg.lstsq(M, b)[0]
+        Fstar = 0.5 * float(np.sum((M @ xs - b) ** 2))
+        F0 = 0.5 * float(b @ b)
+        base = None
+        for tau in taus:
+            with pc.Problem(A.astype("f64"), b, 0.0, tau, seed=0) as p:
+                beta = p.info()["beta"]
+                chunk = max(1, -(-n // (8 * tau)))
+                k = steps_to_eps(p, Fstar, F0, eps, chunk, 2_000_000)
+            if tau == 1:
+                base = k
+            rows.append({"omega": omega, "tau": tau, "beta": beta, "steps": k, "chunk": chunk,
+                         "theory_speedup": tau / beta,
+                         "empirical_speedup": (base / k) if (base and k > 0) else None})
+            print(f"[bench] omega {omega} tau {tau}: beta {beta:.4f}, {k} steps, theory {tau / beta:.2f}, "
+                  f"empirical {rows[-1]['empirical_speedup']}", file=sys.stderr, flush=True)
+    out = {"mode": "theory", "unit": "steps to F - F* <= 1e-6 (F(x_0) - F*)", "data": "synthetic",
+           "dtype": "f64", "seconds": time.perf_counter() - t0,
+           "config": {"m": m, "n": n, "lambda": 0.0, "values": "ones, omega per row, 3 omega per column",
+                      "b": "N(0,1)", "sampling": "tau-nice", "seed": 0},
+           "parity": "unpinned (the paper prints a figure only)", "results": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -782,14 +845,15 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models", "path", "group",
-                             "adjoint"],
+                             "adjoint", "theory"],
                     help="single: one instance (default); batched: the uneven lambda path; "
                          "dtypes: time to gap with float64 / float32 / bf16 values; taus: tau sweep "
                          "on both 1e7-column instances; samplings: nice / independent / binomial / "
                          "masked slots; async: asynchronous variant vs synchronous steps; models: "
                          "logistic regression and the SVM dual; path: warm-started regularisation path; "
                          "group: group LASSO with blocks of 4 columns; adjoint: forward solve and "
-                         "d loss/d (b, lambda) on the training matrix")
+                         "d loss/d (b, lambda) on the training matrix; theory: iterations to 1e-6 "
+                         "against tau / beta on 3000 x 1000 matrices with omega ones per row")
     ap.add_argument("--count", type=int, default=64, help="problems in the batched mode")
     ap.add_argument("--check-steps", type=int, default=64, help="batched mode: steps between gap checks")
     args = ap.parse_args()
@@ -820,6 +884,8 @@ def main() -> int:
         return run_group(args)
     if args.mode == "adjoint":
         return run_adjoint(args)
+    if args.mode == "theory":
+        return run_theory(args)
 
     import numpy as np
     import torch

@@ -103,3 +103,15 @@ def test_host_generator_columns_and_instance():
     np.testing.assert_allclose(biggen.host_b_at(5, m, n, d, K, 0.01, sel, dtype="f64"), b[sel], rtol=0, atol=1e-15)
     A2, b2, x2 = biggen.host_instance(m, n, d, K, 0.01, seed=5, dtype="f64")
     assert np.array_equal(A2.row_idx, A.row_idx) and np.array_equal(b2, b) and np.array_equal(x2, xstar)
+
+
+def test_biregular_matrix_degrees():
+    from workloads import biregular_matrix
+    for omega in (1, 5, 50):
+        A = biregular_matrix(300, 100, omega, np.random.default_rng(omega))
+        assert np.all(np.diff(A.col_ptr) == 3 * omega)
+        assert np.all(np.bincount(A.row_idx, minlength=300) == omega)
+        for i in range(A.n):
+            r = A.row_idx[A.col_ptr[i]:A.col_ptr[i + 1]]
+            assert np.unique(r).size == r.size
+        assert np.all(A.values == 1.0)

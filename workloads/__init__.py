@@ -12,6 +12,7 @@ from .lasso import (  # noqa: F401
     random_csc_ragged,
     planted_lasso,
     tightness_matrix,
+    biregular_matrix,
     separable_matrix,
     orthonormal_block_hadamard,
     dense_to_csc,

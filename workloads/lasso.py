@@ -228,6 +228,39 @@ def tightness_matrix(n: int, omega: int, k: int, row_values: Optional[np.ndarray
     return dense_to_csc(M)
 
 
+def biregular_matrix(m: int, n: int, omega: int, rng: np.random.Generator) -> CSC:
+    """Random 0-1 matrix with exactly ``omega`` ones in every row and
+    m*omega/n in every column (a random biregular pattern: the column slots,
+    each column repeated m*omega/n times, are shuffled and dealt to the rows
+    omega at a time; a column repeated within a row is swapped with a slot of
+    another row until no row repeats one).  The matrix of the tightness
+    remark after the DSO theorem with its pattern drawn at random instead of
+    cyclically."""
+    if (m * omega) % n or omega > n:
+        raise ValueError("m*omega must be a multiple of n and omega <= n")
+    k = m * omega // n
+    slots = rng.permutation(np.repeat(np.arange(n, dtype=np.int64), k)).reshape(m, omega)
+    for _ in range(10000):
+        srt = np.sort(slots, axis=1)
+        bad = np.nonzero(np.any(srt[:, 1:] == srt[:, :-1], axis=1))[0]
+        if bad.size == 0:
+            break
+        for j in bad:
+            row = slots[j]
+            _, first = np.unique(row, return_index=True)
+            for t in np.setdiff1d(np.arange(omega), first):
+                j2, t2 = int(rng.integers(m)), int(rng.integers(omega))
+                slots[j, t], slots[j2, t2] = slots[j2, t2], slots[j, t]
+    else:
+        raise RuntimeError("could not remove repeated columns")
+    rows = np.repeat(np.arange(m, dtype=np.int64), omega)
+    cols = slots.ravel()
+    order = np.lexsort((rows, cols))
+    col_ptr = np.zeros(n + 1, dtype=np.int64)
+    col_ptr[1:] = np.cumsum(np.bincount(cols, minlength=n))
+    return CSC(m, n, col_ptr, rows[order].astype(np.int32), np.ones(m * omega))
+
+
 def separable_matrix(n: int, rows_per_col: int, rng: np.random.Generator) -> CSC:
     """Disjoint row supports: column i owns rows [i*r, (i+1)*r); omega = 1."""
     r = rows_per_col
