@@ -838,6 +838,8 @@ def main() -> int:
     ap.add_argument("--tau", type=int, default=1 << 20)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--lanes", type=int, default=0, help="lanes per column (0 = automatic)")
+    ap.add_argument("--gather-route", type=int, default=0, choices=[0, 1, 2],
+                    help="partial derivatives: 0 automatic, 1 by columns, 2 by rows (option gather_route)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap run")
@@ -954,6 +956,8 @@ def main() -> int:
 
     if args.lanes:
         p.set_option("lanes_per_column", args.lanes)
+    if args.gather_route:
+        p.set_option("gather_route", args.gather_route)
     info = p.info()
     spe = info["refresh_every"]
     s_val = {"f32": 4, "bf16": 2, "f64": 8}[args.dtype]
@@ -1012,6 +1016,7 @@ def main() -> int:
         "config": {"workload": workload, "m": A.m, "n": A.n, "nnz": A.nnz, "tau": tau,
                    "omega": info["omega"], "beta": info["beta"], "lambda": inst.lam,
                    "lanes_per_column": info["lanes_per_column"], "refresh_every": spe,
+                   "gather_route": {1: "columns", 2: "rows"}[info["gather_route"]],
                    "device": dev_name},
         "roofline": {"bound": "hbm", "kernel": "k_gather", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,

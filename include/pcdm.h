@@ -99,7 +99,7 @@ typedef struct pcdm_info {
     int32_t lanes_per_column;/* step-kernel schedule: lanes reading one column    */
     int32_t chunks_per_lane; /* ... and 4-entry chunks each lane holds          */
     int32_t sampling;        /* 0 = tau-nice, 1 = tau-independent, 2 = binomial   */
-    int32_t reserved0;
+    int32_t gather_route;    /* partial derivatives: 1 = plain gather, 2 = by rows  */
     double binomial_p;       /* availability p_b of a binomial slot               */
     double expected_set_size;/* E|S_k| of the sampling (drop mask not included)   */
     int64_t mask_len;        /* slots covered by the drop mask (0 = none)         */
@@ -283,6 +283,27 @@ const char *pcdm_last_error(void);
  *                      take one pass, blocks take 2 for 3; 0 (default) = 3
  *                      from 2^24 stored entries, else 2 (below that the
  *                      route's fixed costs exceed a bound pass);
+ *   "gather_route"     how a step's partial derivatives g_i = a_i^T r are
+ *                      read: 1 = by columns (every sampled column's entries,
+ *                      then r at their rows); 2 = by rows: the step's entries
+ *                      are first dealt into bins by (row range, window of
+ *                      2^18 rows), then r is read window by window, eight
+ *                      row ranges in parallel, and the per-range partial sums
+ *                      are added per slot (same g_i up to the order of the
+ *                      float32 additions; for float32 / bf16 LASSO problems
+ *                      with equal column lengths of at most 32 entries and
+ *                      the tau-nice sampling without a drop mask; otherwise
+ *                      steps take route 1).  Route 2 needs
+ *                      8 ceil(tau/1024) * 8 ceil(m/2^21) * cap + 48 tau bytes.
+ *                      It reads each line of r about once per step instead
+ *                      of once per entry, but its three launches are bound by
+ *                      latency; 0 (default) = 1.  pcdm_info.gather_route
+ *                      reports the route in effect;
+ *   "bin_capacity"     route 2: entries per bin (0 = default: the mean count
+ *                      for rows spread evenly, plus seven standard deviations
+ *                      and 16, rounded up to 16).  A step whose bins overflow
+ *                      is taken by route 1 instead, so results do not depend
+ *                      on it;
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
  *                      settings of pcdm_grad_backward's solve (see there);

@@ -39,7 +39,7 @@ class pcdm_info(ctypes.Structure):
                 ("stored_nnz", ctypes.c_int64), ("beta", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("atb_inf", ctypes.c_double), ("dtype", ctypes.c_int32), ("beta_rule", ctypes.c_int32),
                 ("lanes_per_column", ctypes.c_int32), ("chunks_per_lane", ctypes.c_int32),
-                ("sampling", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("binomial_p", ctypes.c_double),
+                ("sampling", ctypes.c_int32), ("gather_route", ctypes.c_int32), ("binomial_p", ctypes.c_double),
                 ("expected_set_size", ctypes.c_double), ("mask_len", ctypes.c_int64),
                 ("narrow_below", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("loss", ctypes.c_int32),
                 ("reserved1", ctypes.c_int32),

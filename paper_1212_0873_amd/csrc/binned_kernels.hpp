@@ -1,0 +1,402 @@
+// binned_kernels.hpp -- the partial derivatives of a step taken by rows: a
+// route for residuals far larger than the caches.
+//
+// The plain gather reads, for every sampled coordinate i, r at the rows of
+// column i.  With r of hundreds of MB and S_k drawn uniformly, those reads
+// land on random 128-byte lines, each fetched from HBM for one 4-byte value,
+// although a large step touches most lines of r several times.  Here the
+// step's entries are first regrouped by row, so r is read window by window
+// and every line serves all the entries of the step that fall in it:
+//
+//   k_bin      (one workgroup per 1024 consecutive slots): draws the slots'
+//              coordinates (tau-nice, as the plain gather), keeps x_i and
+//              1/L_i of each slot, and deals the column entries into
+//              sub-bins keyed by (row range, row window), in LDS first and
+//              then as contiguous runs in the workgroup's own part of `bins`;
+//   k_bin_dot  (one workgroup per (row range, block of 16384 slots)): walks
+//              the windows of its row range in order, reading its slots'
+//              entries from the sub-bins, r at their rows, and summing
+//              value * r into per-slot LDS accumulators; writes one partial
+//              derivative per (row range, slot);
+//   k_bin_prox (one lane per slot): adds the partials of the row ranges and
+//              takes the update as the plain gather does.
+//
+// Row ranges are eight, one per XCD: workgroup b of k_bin_dot takes range
+// b mod 8, the XCD it is dispatched to (workgroups are dealt to the XCDs in
+// turn; checked on the device with the XCC id register), so the workgroups
+// of one XCD share their windows through that XCD's L2 while the others read
+// other rows.
+// The sum g_i = a_i^T r is the same as the plain gather's up to the order of
+// the float32 additions.
+//
+// Sub-bins have a fixed capacity (a few standard deviations above the mean
+// count of a uniform matrix).  A step in which any sub-bin overflows sets a
+// flag that k_bin_prox reads: it then computes that step by the plain gather
+// instead, so the result never depends on the capacity.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace pcdm {
+
+constexpr int kBinRanges = 8;
+constexpr int kBinWinBits = 18;  // window = 2^18 rows (1 MB of float32 r)
+constexpr uint32_t kBinWinMask = (1u << kBinWinBits) - 1u;
+constexpr int kBinBlockBits = 14;  // k_bin_dot: 2^14 slots per workgroup
+constexpr int kBinBlock = 1 << kBinBlockBits;
+constexpr int kBinSlotsA = 1024;  // k_bin: slots per workgroup
+constexpr int kBinHalf = 512;     // k_bin: threads, and slots staged at once
+constexpr int kBinDotThreads = 512;
+constexpr int kBinMaxDpad = 32;   // one 4-entry chunk per lane of an 8-lane group
+constexpr int kBinMaxSub = 1024;  // sub-bins per k_bin workgroup (8 ranges x windows)
+static_assert(kBinWinBits + kBinBlockBits == 32, "key = slot in block | row in window");
+static_assert(kBinBlock % kBinSlotsA == 0, "a k_bin workgroup feeds one k_bin_dot block");
+
+struct BinGeom {
+    int64_t rx;    // rows per range, ceil(m / 8)
+    int32_t nw;    // windows per range
+    int32_t ns;    // sub-bins per k_bin workgroup: 8 * nw
+    int32_t cap;   // entries per sub-bin
+    int32_t dpad;  // entries per record (fixed-length records)
+};
+
+struct BinEntry {
+    uint32_t key;  // slot within its k_bin_dot block << 18 | row within its window
+    float val;
+};
+
+// Dynamic LDS of k_bin: four counters per sub-bin, then per staged entry its
+// key, value, sub-bin and a sorted-order index.
+__host__ __device__ inline size_t bin_lds_bytes(int ns, int dpad)
+{
+    return (size_t)4 * ns * sizeof(int32_t) + (size_t)kBinHalf * dpad * (4 + 4 + 2 + 2);
+}
+
+// Exclusive prefix sum of v[0..cnt) (cnt <= 2 * blockDim.x, blockDim.x a
+// multiple of 64 and at most 1024) into out[]; `wtot` holds one int per wave.
+__device__ __forceinline__ void block_exclusive_scan(const int32_t *v, int32_t *out, int cnt, int32_t *wtot)
+{
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int i0 = 2 * t, i1 = 2 * t + 1;
+    const int32_t a = i0 < cnt ? v[i0] : 0;
+    const int32_t b = i1 < cnt ? v[i1] : 0;
+    int32_t s = a + b, inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += y;
+    }
+    if (lane == 63)
+        wtot[w] = inc;
+    __syncthreads();
+    int32_t before = 0;
+    for (int q = 0; q < w; ++q)
+        before += wtot[q];
+    const int32_t ex = before + inc - s;
+    if (i0 < cnt)
+        out[i0] = ex;
+    if (i1 < cnt)
+        out[i1] = ex + a;
+    __syncthreads();
+}
+
+// In-place exclusive prefix sum of v[0..cnt) for cnt <= 4 * blockDim.x
+// (blockDim.x a multiple of 64, at most 1024): thread t sums a contiguous
+// quarter-run of the array; returns the total.  `wtot` holds one int per wave.
+__device__ __forceinline__ int32_t block_exclusive_scan4(int32_t *v, int cnt, int32_t *wtot)
+{
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6, nwv = (int)(blockDim.x >> 6);
+    const int per = (cnt + (int)blockDim.x - 1) / (int)blockDim.x;  // <= 4
+    const int b0 = t * per;
+    int32_t loc[4] = {0, 0, 0, 0};
+    int32_t s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u < per && b0 + u < cnt) {
+            loc[u] = v[b0 + u];
+            s += loc[u];
+        }
+    int32_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += y;
+    }
+    if (lane == 63)
+        wtot[w] = inc;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int q = 0; q < nwv; ++q) {
+        if (q < w)
+            before += wtot[q];
+        total += wtot[q];
+    }
+    int32_t run = before + inc - s;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u < per && b0 + u < cnt) {
+            v[b0 + u] = run;
+            run += loc[u];
+        }
+    __syncthreads();
+    return total;
+}
+
+// Binning: workgroup a takes slots [1024 a, 1024 a + 1024) of step k in two
+// halves of 512.  Writes id_slot, hdr (x_i, 1/L_i) per slot, the runs of its
+// sub-bins and their counts; sets over[k & 1] if a sub-bin overflows.
+template <typename V>
+__global__ void __launch_bounds__(kBinHalf)
+k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restrict__ ctrl, uint64_t seed,
+      int64_t tau, uint32_t n, int32_t *__restrict__ id_slot, v2d_t *__restrict__ hdr,
+      BinEntry *__restrict__ bins, int32_t *__restrict__ counts, uint32_t *__restrict__ over)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_keys[kNiceRounds];
+    __shared__ int32_t s_wtot[kBinHalf / 64];
+    const int ns = geo.ns, dpad = geo.dpad;
+    const int nstage = kBinHalf * dpad;
+    int32_t *cnt = reinterpret_cast<int32_t *>(smem);
+    int32_t *offs = cnt + ns;
+    int32_t *fill = offs + ns;
+    int32_t *run = fill + ns;
+    uint32_t *stkey = reinterpret_cast<uint32_t *>(run + ns);
+    float *stval = reinterpret_cast<float *>(stkey + nstage);
+    uint16_t *stsub = reinterpret_cast<uint16_t *>(stval + nstage);
+    uint16_t *order = stsub + nstage;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6, gl = lane & 7, grp = lane >> 3;
+    const int64_t a = blockIdx.x;
+    for (int q = t; q < ns; q += kBinHalf) {
+        cnt[q] = 0;
+        fill[q] = 0;
+        run[q] = 0;
+    }
+    const uint64_t k = ctrl->k;
+    const NiceKey key = nice_key_block(seed, k, n, s_keys);  // synchronises the block
+    bool overflow = false;
+    for (int h = 0; h < 2; ++h) {
+        const int64_t slot = a * kBinSlotsA + (int64_t)h * kBinHalf + t;
+        const bool act = slot < tau;
+        int64_t off = 0;
+        if (act) {
+            const uint32_t i = nice_slot((uint32_t)slot, key);
+            id_slot[slot] = (int32_t)i;
+            off = (int64_t)i * lay.stride;
+            hdr[slot] = ld_rec(reinterpret_cast<const v2d_t *>(seg + off));
+        }
+        // entries: in round q the 8 lanes of group grp read column q * 8 + grp
+        // of this wave, one 4-entry chunk each (dpad <= 32); unrolled so that
+        // the loads of all rounds are in flight together
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int o = q * 8 + grp;
+            const int64_t coff = __shfl(off, o);
+            const bool cact = __shfl((int)act, o) != 0;
+            const int sl = w * 64 + o;  // staged column within the half
+            const int e = 4 * gl;
+            if (e < dpad) {
+                int rw[4] = {0, 0, 0, 0};
+                typename ValT<V>::T v[4] = {0, 0, 0, 0};
+                if (cact)
+                    Chunk4<V>::load(seg + coff + kHeader, dpad, e, rw, v);
+                // slot of column sl within its k_bin_dot block
+                const uint32_t sblk =
+                    (uint32_t)(((a * kBinSlotsA + (int64_t)h * kBinHalf + sl)) & (int64_t)(kBinBlock - 1));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int idx = sl * dpad + e + u;
+                    if (cact && v[u] != 0) {
+                        const uint32_t row = (uint32_t)rw[u];
+                        const uint32_t xr = (uint32_t)(row / (uint64_t)geo.rx);
+                        const uint32_t within = row - (uint32_t)((uint64_t)xr * (uint64_t)geo.rx);
+                        const int sub = (int)(xr * (uint32_t)geo.nw + (within >> kBinWinBits));
+                        stkey[idx] = (sblk << kBinWinBits) | (within & kBinWinMask);
+                        stval[idx] = (float)v[u];
+                        stsub[idx] = (uint16_t)sub;
+                        atomicAdd(&cnt[sub], 1);
+                    } else {
+                        stsub[idx] = 0xFFFFu;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        block_exclusive_scan(cnt, offs, ns, s_wtot);  // ends with a barrier
+        const int nvalid = offs[ns - 1] + cnt[ns - 1];
+        for (int idx = t; idx < nstage; idx += kBinHalf) {
+            const uint16_t sub = stsub[idx];
+            if (sub != 0xFFFFu)
+                order[offs[sub] + atomicAdd(&fill[sub], 1)] = (uint16_t)idx;
+        }
+        __syncthreads();
+        for (int j = t; j < nvalid; j += kBinHalf) {
+            const int idx = order[j];
+            const int sub = stsub[idx];
+            const int pos = run[sub] + (j - offs[sub]);
+            if (pos < geo.cap) {
+                BinEntry be;
+                be.key = stkey[idx];
+                be.val = stval[idx];
+                bins[((int64_t)a * ns + sub) * geo.cap + pos] = be;
+            } else {
+                overflow = true;
+            }
+        }
+        __syncthreads();
+        for (int q = t; q < ns; q += kBinHalf) {
+            run[q] += cnt[q];
+            cnt[q] = 0;
+            fill[q] = 0;
+        }
+        __syncthreads();
+    }
+    for (int q = t; q < ns; q += kBinHalf)
+        counts[a * ns + q] = run[q] < geo.cap ? run[q] : geo.cap;
+    if (overflow)
+        atomicOr(over + (k & 1), 1u);
+}
+
+// Per (row range xr = blockIdx.x mod 8, slot block c = blockIdx.x / 8): the
+// range's part of g for the block's slots.  The block's sub-bin runs are
+// taken in window-major order (window tw, then the 16 k_bin workgroups of the
+// block) as one flat list of entries, 512 at a time (one per thread): every
+// block of a range then moves through the range's rows at the same pace, so
+// the rows in use at any moment (about 1.3 MB for the 64 blocks of an XCD)
+// stay in that XCD's L2.  The entries of the next stretch are loaded before
+// r is read for the current one, so the two latencies overlap.  (Measured on
+// the 2e8-row instance: 1024 entries per block at a time, or two windows per
+// stage taken by each wave on its own, let the blocks drift apart and L2
+// misses rose from 8.0e6 to 1.3e7-1.6e7 per launch.)
+constexpr int kBinPerBlock = kBinBlock / kBinSlotsA;  // k_bin workgroups per block (16)
+constexpr int kBinMaxRuns = (kBinMaxSub / kBinRanges) * kBinPerBlock;
+
+// Entry j of the block's flat list (j < pre[nruns]): its bin entry and the
+// first row of its window.
+__device__ __forceinline__ void bin_flat_entry(const BinEntry *__restrict__ bins, const int32_t *pre, int nruns,
+                                               const BinGeom &geo, int xr, int64_t a0, int32_t j, BinEntry &be,
+                                               uint32_t &rowb)
+{
+    // the run holding j: the last q with pre[q] <= j
+    int lo = 0, hi = nruns;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= j)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int tw = lo / kBinPerBlock;
+    const int64_t sb = (a0 + (lo % kBinPerBlock)) * geo.ns + (int64_t)xr * geo.nw + tw;
+    // entries are read once: keep them out of L2, which holds the rows of r
+    const uint64_t raw =
+        __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(bins + sb * geo.cap + (j - pre[lo])));
+    be.key = (uint32_t)raw;
+    be.val = __uint_as_float((uint32_t)(raw >> 32));
+    rowb = (uint32_t)((int64_t)xr * geo.rx + ((int64_t)tw << kBinWinBits));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBinDotThreads)
+k_bin_dot(const BinEntry *__restrict__ bins, const int32_t *__restrict__ counts, const T *__restrict__ r,
+          BinGeom geo, int64_t tau, int64_t na, T *__restrict__ partial)
+{
+    __shared__ float acc[kBinBlock];
+    __shared__ int32_t pre[kBinMaxRuns + 1];
+    __shared__ int32_t s_wtot[kBinDotThreads / 64];
+    const int t = threadIdx.x;
+    const int xr = (int)(blockIdx.x % kBinRanges);
+    const int64_t c = blockIdx.x / kBinRanges;
+    const int64_t a0 = c * kBinPerBlock;
+    const int ns = geo.ns, nw = geo.nw;
+    const int nruns = nw * kBinPerBlock;
+    for (int j = t; j < kBinBlock; j += kBinDotThreads)
+        acc[j] = 0.0f;
+    // run q = tw * 16 + u: sub-bin (workgroup a0 + u, range xr, window tw)
+    for (int q = t; q < nruns; q += kBinDotThreads) {
+        const int u = q / nw, tw = q % nw;  // consecutive threads: consecutive windows of one workgroup
+        const int64_t a = a0 + u;
+        pre[tw * kBinPerBlock + u] = a < na ? counts[a * ns + (int64_t)xr * nw + tw] : 0;
+    }
+    __syncthreads();
+    const int32_t total = block_exclusive_scan4(pre, nruns, s_wtot);
+    if (t == 0)
+        pre[nruns] = total;
+    __syncthreads();
+    BinEntry cur{0u, 0.0f};
+    uint32_t rowb = 0;
+    if (t < total)
+        bin_flat_entry(bins, pre, nruns, geo, xr, a0, t, cur, rowb);
+    for (int32_t j = t; j < total; j += kBinDotThreads) {
+        const T rv = load_row(r, (int)(rowb + (cur.key & kBinWinMask)));
+        BinEntry nxt{0u, 0.0f};
+        uint32_t nrowb = 0;
+        if (j + kBinDotThreads < total)
+            bin_flat_entry(bins, pre, nruns, geo, xr, a0, j + kBinDotThreads, nxt, nrowb);
+        atomicAdd(&acc[cur.key >> kBinWinBits], (float)(cur.val * rv));
+        cur = nxt;
+        rowb = nrowb;
+    }
+    __syncthreads();
+    for (int j = t; j < kBinBlock; j += kBinDotThreads) {
+        const int64_t s = c * kBinBlock + j;
+        if (s < tau)
+            partial[(int64_t)xr * tau + s] = (T)acc[j];
+    }
+}
+
+// The update of every slot from the summed partials, or, when the binning of
+// this step overflowed, the whole step by the plain gather.
+template <typename V, int G, int C>
+__global__ void __launch_bounds__(kBlock)
+k_bin_prox(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__restrict__ r,
+           double *__restrict__ xm, int32_t *__restrict__ id_slot, typename ValT<V>::T *__restrict__ delta_slot,
+           const Ctrl *__restrict__ ctrl, uint64_t *__restrict__ nz_part, uint64_t seed, int64_t tau, uint32_t n,
+           double inv_beta, ProxParams pp, const v2d_t *__restrict__ hdr,
+           const typename ValT<V>::T *__restrict__ partial, uint32_t *__restrict__ over)
+{
+    using T = typename ValT<V>::T;
+    __shared__ uint32_t s_keys[kNiceRounds];
+    __shared__ uint64_t s_red[kBlock / 64];
+    const uint64_t k = ctrl->k;
+    const bool plain = over[k & 1] != 0;
+    uint64_t nz = 0;
+    if (plain) {
+        const NiceKey key = nice_key_block(seed, k, n, s_keys);
+        const SlotDraw sd = slot_draw_for(plan_nice(), seed, k);
+        const TileLanes<G> tl;
+        for (int64_t base = wave_global_id() * 64; base < tau; base += wave_count() * 64)
+            gather_tile<V, G, C, kLossSquare>(seg, lay, r, xm, id_slot, delta_slot, key, sd, tl, base, tau,
+                                              inv_beta, pp, nz);
+    } else {
+        for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < tau; s += (int64_t)gridDim.x * kBlock) {
+            T g = T(0);
+#pragma unroll
+            for (int xr = 0; xr < kBinRanges; ++xr)
+                g += partial[(int64_t)xr * tau + s];
+            const v2d_t hv = hdr[s];
+            const double xi = hv.x;
+            const double xn = model_prox(xi, (double)g * pp.gscale, hv.y * inv_beta, pp);
+            const double d = xn - xi;
+            delta_slot[s] = (T)d;
+            if (d != 0.0) {
+                const int32_t i = id_slot[s];
+                __builtin_nontemporal_store(xn, reinterpret_cast<double *>(seg + (int64_t)i * lay.stride));
+                __builtin_nontemporal_store(xn, xm + i);
+                ++nz;
+            }
+        }
+    }
+    const uint64_t tot = block_sum_u64(nz, s_red);
+    if (threadIdx.x == 0 && tot)
+        nz_part[blockIdx.x] += tot;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        over[(k + 1) & 1] = 0u;  // the next step's flag; nobody reads it during this step
+}
+
+}  // namespace pcdm

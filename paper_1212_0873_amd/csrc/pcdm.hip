@@ -18,6 +18,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "binned_kernels.hpp"
 #include "group_kernels.hpp"
 #include "kernels.hpp"
 #include "pcdm.h"
@@ -193,6 +194,18 @@ struct pcdm_problem {
     int64_t adj_last_epochs = 0;
     double adj_last_resid = 0.0;
     std::vector<hipEvent_t> event_pool;
+
+    // row-binned route of the partial derivatives (binned_kernels.hpp)
+    int gather_route = 0;     // option: 0 automatic, 1 plain gather, 2 binned where eligible
+    bool binned = false;      // route in effect
+    int64_t bin_cap_opt = 0;  // option: entries per sub-bin (0 = from the expected count)
+    BinGeom bgeo{};
+    int64_t bin_tau = 0;      // tau the buffers were sized for
+    void *bins = nullptr;     // [ceil(tau/1024) * ns * cap] BinEntry
+    int32_t *bcounts = nullptr;
+    void *bhdr = nullptr;     // [tau] {x_i, 1/L_i}
+    void *bpart = nullptr;    // [8 * tau] working type
+    uint32_t *bover = nullptr;  // [2] overflow flags by step parity
 };
 
 namespace {
@@ -235,7 +248,8 @@ void free_problem(pcdm_problem *P)
         (void)hipEventDestroy(e);
     void *bufs[] = {P->seg, P->pc, P->x, P->r, P->r64, P->b64, P->id_slot,
                     P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim, P->bp, P->invlb, P->dx,
-                    P->t32, P->ub, P->rold, P->nrm, P->inc, P->cnt};
+                    P->t32, P->ub, P->rold, P->nrm, P->inc, P->cnt, P->bins, P->bcounts, P->bhdr, P->bpart,
+                    P->bover};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -455,6 +469,101 @@ int ensure_slots(pcdm_problem *P, int64_t tau)
     return PCDM_OK;
 }
 
+void free_bins(pcdm_problem *P)
+{
+    void *b[] = {P->bins, P->bcounts, P->bhdr, P->bpart, P->bover};
+    for (void *q : b)
+        if (q)
+            (void)hipFree(q);
+    P->bins = nullptr;
+    P->bcounts = nullptr;
+    P->bhdr = nullptr;
+    P->bpart = nullptr;
+    P->bover = nullptr;
+    P->bin_tau = 0;
+}
+
+// Whether the row-binned route can take this problem's steps, and why not.
+const char *bin_ineligible(const pcdm_problem *P)
+{
+    if (P->loss != kLossSquare || P->group)
+        return "the binned route is built for the LASSO over coordinates";
+    if (P->dtype == PCDM_F64)
+        return "the binned route takes float32 or bf16 values";
+    if (P->lay.fixed_dpad < 1 || P->lay.fixed_dpad > kBinMaxDpad)
+        return "the binned route needs equal column lengths of at most 32 entries";
+    if (P->sampling != kSampleNice || P->mask)
+        return "the binned route takes the tau-nice sampling without a drop mask";
+    const int64_t rx = ceil_div(P->m, kBinRanges);
+    const int64_t ns = kBinRanges * ceil_div(rx, (int64_t)1 << kBinWinBits);
+    if (ns > kBinMaxSub || bin_lds_bytes((int)ns, (int)P->lay.fixed_dpad) > (size_t)160 * 1024)
+        return "too many rows for the binned route";
+    return nullptr;
+}
+
+// Decide the route of the partial derivatives and size its buffers
+// (called from API calls only, never inside a captured step).
+int route_update(pcdm_problem *P)
+{
+    // automatic (0) takes the plain gather: on every shape measured so far the
+    // binned route's three launches took longer than the plain gather (the
+    // 1e10-entry instance at tau = 2^20: about 480 us against 427 us)
+    const bool ok = bin_ineligible(P) == nullptr;
+    const bool want = P->gather_route == 2;
+    if (!(ok && want)) {
+        P->binned = false;
+        free_bins(P);
+        return PCDM_OK;
+    }
+    BinGeom g;
+    g.rx = ceil_div(P->m, kBinRanges);
+    g.nw = (int32_t)ceil_div(g.rx, (int64_t)1 << kBinWinBits);
+    g.ns = kBinRanges * g.nw;
+    g.dpad = (int32_t)P->lay.fixed_dpad;
+    if (P->bin_cap_opt > 0) {
+        g.cap = (int32_t)P->bin_cap_opt;
+    } else {
+        // mean count of a sub-bin when rows are uniform, plus 7 standard deviations
+        const double mu = (double)kBinSlotsA * g.dpad / g.ns;
+        g.cap = (int32_t)(16 * ceil_div((int64_t)std::ceil(mu + 7.0 * std::sqrt(mu) + 16.0), 16));
+    }
+    if (P->bins && P->bin_tau == P->tau && P->bgeo.ns == g.ns && P->bgeo.cap == g.cap && P->bgeo.dpad == g.dpad &&
+        P->bgeo.rx == g.rx) {
+        P->binned = true;
+        return PCDM_OK;
+    }
+    free_bins(P);
+    P->binned = false;
+    const int64_t na = ceil_div(P->tau, kBinSlotsA);
+    const size_t lds = bin_lds_bytes(g.ns, g.dpad);
+    hipError_t e = hipMalloc(&P->bins, (size_t)na * g.ns * g.cap * sizeof(BinEntry));
+    if (e == hipSuccess)
+        e = hipMalloc(&P->bcounts, (size_t)na * g.ns * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&P->bhdr, (size_t)P->tau * 16);
+    if (e == hipSuccess)
+        e = hipMalloc(&P->bpart, (size_t)kBinRanges * P->tau * P->tbytes);
+    if (e == hipSuccess)
+        e = hipMalloc(&P->bover, 2 * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemset(P->bover, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = P->dtype == PCDM_BF16
+                ? hipFuncSetAttribute((const void *)k_bin<bf16s>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                : hipFuncSetAttribute((const void *)k_bin<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+        free_bins(P);
+        (void)hipGetLastError();
+        if (P->gather_route == 2)
+            return hip_fail(e, "binned route set-up");
+        return PCDM_OK;  // automatic choice: keep the plain gather
+    }
+    P->bgeo = g;
+    P->bin_tau = P->tau;
+    P->binned = true;
+    return PCDM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Per value type operations.
 // ---------------------------------------------------------------------------
@@ -462,8 +571,40 @@ int ensure_slots(pcdm_problem *P, int64_t tau)
 template <typename V> struct Ops {
     using T = typename ValT<V>::T;
 
+    // Partial derivatives by rows (k_bin, k_bin_dot, k_bin_prox), then the scatter.
+    template <int G, int C> static void launch_binned(pcdm_problem *P, hipStream_t s)
+    {
+        const BinGeom geo = P->bgeo;
+        const int64_t na = ceil_div(P->tau, kBinSlotsA);
+        const int64_t nb = ceil_div(P->tau, kBinBlock);
+        hipEvent_t t0 = clock_start(P, s);
+        hipLaunchKernelGGL((k_bin<V>), dim3((unsigned)na), dim3(kBinHalf), bin_lds_bytes(geo.ns, geo.dpad), s,
+                           (const char *)P->seg, P->lay, geo, (const Ctrl *)P->ctrl, P->seed, P->tau, (uint32_t)P->n,
+                           P->id_slot, (v2d_t *)P->bhdr, (BinEntry *)P->bins, P->bcounts, P->bover);
+        hipLaunchKernelGGL((k_bin_dot<T>), dim3((unsigned)(kBinRanges * nb)), dim3(kBinDotThreads), 0, s,
+                           (const BinEntry *)P->bins, (const int32_t *)P->bcounts, (const T *)P->r, geo, P->tau, na,
+                           (T *)P->bpart);
+        const int grid = grid_for(P->tau, kBlock, P->nblk_max);
+        hipLaunchKernelGGL((k_bin_prox<V, G, C>), dim3(grid), dim3(kBlock), 0, s, P->seg, P->lay, (const T *)P->r,
+                           P->x, P->id_slot, (T *)P->delta_slot, (const Ctrl *)P->ctrl, P->nz_part, P->seed, P->tau,
+                           (uint32_t)P->n, 1.0 / P->beta, prox_params(P), (const v2d_t *)P->bhdr,
+                           (const T *)P->bpart, P->bover);
+        clock_stop(P, CLK_GATHER, t0, s);
+        const int sgrid = grid_for(P->tau, kScatterSpan, P->nblk_max);
+        hipEvent_t t1 = clock_start(P, s);
+        hipLaunchKernelGGL((k_scatter<V, G>), dim3(sgrid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                           (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl, P->tau);
+        clock_stop(P, CLK_SCATTER, t1, s);
+    }
+
     template <int G, int C, int Loss> static void launch_step(pcdm_problem *P, hipStream_t s)
     {
+        if constexpr (Loss == kLossSquare && !std::is_same<V, double>::value) {
+            if (P->binned && P->bins && P->bin_tau == P->tau) {
+                launch_binned<G, C>(P, s);
+                return;
+            }
+        }
         if (P->tau < P->narrow_below) {
             // one slot per group of G lanes
             const int grid = grid_for(P->tau * G, kBlock, P->nblk_max);
@@ -1174,6 +1315,7 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
         HIP_TRY(hipMemcpy(&hc, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
         P->atb_inf = hc.scal[3];
     }
+    PCDM_TRY(route_update(P));
     guard.p = nullptr;
     *out = P;
     return PCDM_OK;
@@ -1212,6 +1354,15 @@ std::vector<unsigned char> step_signature(const pcdm_problem *P)
     put(P->id_slot);
     put(P->delta_slot);
     put(P->dx);
+    put(P->binned);
+    put(P->bins);
+    put(P->bcounts);
+    put(P->bhdr);
+    put(P->bpart);
+    put(P->bover);
+    put(P->bgeo.cap);
+    put(P->bgeo.ns);
+    put(P->bin_tau);
     return sig;
 }
 
@@ -1408,6 +1559,7 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         PCDM_TRY(ensure_slots(h, t));
         h->tau = t;
         compute_beta(h);
+        PCDM_TRY(route_update(h));
     } else if (k == "lanes_per_column" || k == "chunks_per_lane") {
         const int v = (int)value;
         if ((double)v != value || v < 0)
@@ -1437,6 +1589,7 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         }
         h->sampling = v;
         compute_beta(h);
+        PCDM_TRY(route_update(h));
     } else if (k == "binomial_p") {
         if (!(value > 0.0 && value <= 1.0))
             return fail(PCDM_EINVAL, "binomial_p must be in (0, 1]");
@@ -1489,6 +1642,23 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
             h->clocks[c].total_ms = 0.0;
         }
         h->timing = value != 0.0;
+    } else if (k == "gather_route") {
+        if (value != 0.0 && value != 1.0 && value != 2.0)
+            return fail(PCDM_EINVAL, "gather_route must be 0 (automatic), 1 (plain gather) or 2 (binned)");
+        if (value == 2.0) {
+            const char *why = bin_ineligible(h);
+            if (why)
+                return fail(PCDM_EINVAL, why);
+        }
+        HIP_TRY(hipStreamSynchronize(h->last_stream));  // queued steps may use the buffers
+        h->gather_route = (int)value;
+        PCDM_TRY(route_update(h));
+    } else if (k == "bin_capacity") {
+        if (!(value >= 0.0) || value > 65536.0 || value != std::floor(value))
+            return fail(PCDM_EINVAL, "bin_capacity must be an integer in [0, 65536]");
+        HIP_TRY(hipStreamSynchronize(h->last_stream));
+        h->bin_cap_opt = (int64_t)value;
+        PCDM_TRY(route_update(h));
     } else if (k == "reset_counters") {
         hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(kBlock), 0, h->last_stream, h->nz_part,
                            (uint64_t)0, (int64_t)h->nblk_max);
@@ -1527,6 +1697,7 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->lanes_per_column = h->lanes;
     out->chunks_per_lane = h->chunks;
     out->sampling = h->sampling;
+    out->gather_route = h->binned ? 2 : 1;
     out->binomial_p = h->pb;
     out->expected_set_size = expected_set_size(h);
     out->mask_len = h->mask_len;
@@ -2057,13 +2228,13 @@ int pcdm_set_slot_mask(pcdm_problem *h, const uint8_t *mask, int64_t len, int32_
     h->mask = nullptr;
     h->mask_len = 0;
     if (len == 0)
-        return PCDM_OK;
+        return route_update(h);
     HIP_TRY(hipMalloc(&h->mask, (size_t)len));
     HIP_TRY(hipMemcpyAsync(h->mask, mask, (size_t)len, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            s));
     HIP_TRY(hipStreamSynchronize(s));
     h->mask_len = len;
-    return PCDM_OK;
+    return route_update(h);
 }
 
 }  // extern "C"

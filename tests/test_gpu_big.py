@@ -112,7 +112,8 @@ def big(pc):
     inf = p.info()
     p.set_option("lambda", 0.05 * inf["atb_inf"])
     _say(f"created ({time.time() - t0:.0f} s): omega {inf['omega']}, beta {inf['beta']:.6f}, "
-         f"||A^T b||_inf {inf['atb_inf']:.15e}")
+         f"||A^T b||_inf {inf['atb_inf']:.15e}, gather route {inf['gather_route']}")
+    assert inf["gather_route"] == 1  # plain gather by default
     yield {"p": p, "host": host, "thread": th, "t0": t0}
     p.close()
     torch.cuda.empty_cache()
@@ -145,7 +146,8 @@ def test_full_size_create_matches_host_pass(big):
 
 
 def test_full_size_three_steps_match_oracle(big):
-    """Three steps of tau = 2^20 at 1e10 nonzeros: after every step F (float64
+    """Three steps of tau = 2^20 at 1e10 nonzeros (the second one with the
+    partial derivatives taken by rows): after every step F (float64
     refresh on the device) against the oracle's F on its own float64 r and x,
     every coordinate of S_k against the oracle's, coordinates outside every
     S_k still 0, and the count of nonzero updates of step 0 (from x = 0 a
@@ -172,6 +174,9 @@ def test_full_size_three_steps_match_oracle(big):
             absdot = np.add.reduceat(np.abs(vals) * np.abs(ref.r[rows]), cp[:-1])
             edge = int(np.count_nonzero(np.abs(np.abs(g) - lam) <= (d + 3) * 2.0 ** -24 * absdot))
         changed = ref.step_with_columns(S, cp, rows, vals)
+        # step 1 takes the partial derivatives by rows (option gather_route 2)
+        p.set_option("gather_route", 2 if k == 1 else 1)
+        assert p.info()["gather_route"] == (2 if k == 1 else 1)
         p.step(1)
         if k == 0:
             got = p.info()["nonzero_updates"]
