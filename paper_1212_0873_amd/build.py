@@ -11,6 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcdm.so")
 # memory-system calibration kernels used by bench.py (not the method)
 CALIB_LIB = os.path.join(HERE, "libpcdm_calib.so")
+# host entry points to the incremental bound's constants, for the CPU tests
+CHECK_LIB = os.path.join(HERE, "libpcdm_check.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no v_pk_*_f32 generated for ordinary float code.
@@ -30,6 +32,11 @@ def calib_sources():
     return [os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith(".hip")]
 
 
+def check_sources():
+    d = os.path.join(CSRC, "check")
+    return [os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith(".hip")]
+
+
 def _compile(srcs, out, verbose):
     tmp = out + f".tmp{os.getpid()}"
     cmd = [HIPCC, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
@@ -40,11 +47,13 @@ def _compile(srcs, out, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every .hip source directly under csrc/ into libpcdm.so and the
-    calibration kernels under csrc/calib/ into libpcdm_calib.so (always
-    rebuilds both)."""
+    """Compile every .hip source directly under csrc/ into libpcdm.so, the
+    calibration kernels under csrc/calib/ into libpcdm_calib.so and the
+    host checks under csrc/check/ into libpcdm_check.so (always rebuilds
+    all three)."""
     _compile(sources(), LIB, verbose)
     _compile(calib_sources(), CALIB_LIB, verbose)
+    _compile(check_sources(), CHECK_LIB, verbose)
     return LIB
 
 

@@ -404,12 +404,8 @@ k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc
             inc = incremental && ist[4 * j + 3] != 0.0;
             if (inc) {
                 const double dmax = d.lay.fixed_dpad ? (double)d.lay.fixed_dpad : (double)d.m;
-                const double gam = (dmax + 2.0) * 0x1p-52;
-                // |fl(x - o)| understates |x - o| by at most a relative 2^-53
-                const double dlt = dacc[4 * j] * (1.0 + 0x1p-50);
-                const double rmax = fmax(dacc[4 * j + 3], dacc[4 * j + 1]);
-                D = (dlt + 2.0 * gam * rmax) * (1.0 + 0x1p-40);
-                lo = (ist[4 * j] - ist[4 * j + 1] * D) * (1.0 - 0x1p-40) - 0x1p-1000;
+                D = inc_shift(dacc[4 * j], fmax(dacc[4 * j + 3], dacc[4 * j + 1]), inc_gamma(dmax));
+                lo = inc_lower(ist[4 * j], ist[4 * j + 1], D);
             }
         }
         const BatchInst &d = desc[j];
@@ -422,7 +418,7 @@ k_batch_col_obj(const char *__restrict__ seg, const BatchInst *__restrict__ desc
             ax += fabs(xm[d.col_base + col]);
             cand = true;
             if (inc) {
-                bnd = (double)ub[d.col_base + col] * (1.0 + 0x1p-40) + (double)nrm[d.col_base + col] * D;
+                bnd = inc_moved((double)ub[d.col_base + col], (double)nrm[d.col_base + col], D);
                 cand = !(bnd < lo);
             }
             if (cand)

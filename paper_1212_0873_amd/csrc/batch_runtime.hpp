@@ -164,7 +164,7 @@ template <typename V> struct BatchOps {
         const double dmax = d.lay.fixed_dpad ? (double)d.lay.fixed_dpad : (double)d.m;
         const int g = grid_for(d.n, kBlock, B->nblk_max);
         hipLaunchKernelGGL((k_col_norms<V, 8>), dim3(g), dim3(kBlock), 0, s, (const char *)B->seg + d.rec_base, d.lay,
-                           d.n, 1.0 + (dmax + 8.0) * 0x1p-52, B->nrmc + d.col_base, part);
+                           d.n, inc_l1_factor(dmax), B->nrmc + d.col_base, part);
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, g, 1, 1, B->ist + 4 * j + 1);
     }
 

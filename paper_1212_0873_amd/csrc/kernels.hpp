@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "inc_bound.hpp"
 #include "sampler.hpp"
 
 namespace pcdm {
@@ -1344,11 +1345,9 @@ __global__ void k_inc_prepare(double *__restrict__ inc, double nrm_max, double g
 {
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
-    const double dlt = inc[1] * (1.0 + 0x1p-50);
-    const double rmax = fmax(inc[2], inc[3]);
-    const double D = (dlt + 2.0 * gam * rmax) * (1.0 + 0x1p-40);
+    const double D = inc_shift(inc[1], fmax(inc[2], inc[3]), gam);
     inc[4] = D;
-    inc[5] = (inc[0] - nrm_max * D) * (1.0 - 0x1p-40) - 0x1p-1000;
+    inc[5] = inc_lower(inc[0], nrm_max, D);
 }
 
 __device__ __forceinline__ float round_up_f32(double v)
@@ -1370,7 +1369,7 @@ k_inc_count(const float *__restrict__ ub, const float *__restrict__ nrm, int64_t
     const double D = inc[4], lo = inc[5];
     uint64_t c = 0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        c += !((double)ub[i] * (1.0 + 0x1p-40) + (double)nrm[i] * D < lo);
+        c += !(inc_moved((double)ub[i], (double)nrm[i], D) < lo);
     c = block_sum_u64(c, s_red);
     if (threadIdx.x == 0 && c)
         atomicAdd(cnt, (unsigned long long)c);
@@ -1395,7 +1394,7 @@ k_atr_inc(const char *__restrict__ seg, Layout lay, const double *__restrict__ r
         double bnd = 0.0;
         bool cand = false;
         if (col < n) {
-            bnd = (double)ub[col] * (1.0 + 0x1p-40) + (double)nrm[col] * D;
+            bnd = inc_moved((double)ub[col], (double)nrm[col], D);
             cand = !(bnd < lo);
         }
         if (__any(cand)) {

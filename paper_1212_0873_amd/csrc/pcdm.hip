@@ -934,14 +934,14 @@ template <typename V> struct Ops {
         const int grid = grid_for(P->n, kBlock, P->nblk_max);
         const double dmax = P->lay.fixed_dpad ? (double)P->lay.fixed_dpad : (double)P->m;
         hipLaunchKernelGGL((k_col_norms<V, 8>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay, P->n,
-                           1.0 + (dmax + 8.0) * 0x1p-52, P->nrm, P->part2);
+                           inc_l1_factor(dmax), P->nrm, P->part2);
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, s, (const double *)P->part2, grid, 1, 1,
                            P->ctrl->scal + 5);
         double v = 0.0;
         HIP_TRY(hipMemcpyAsync(&v, P->ctrl->scal + 5, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         P->nrm_max = v;
-        P->gam = (dmax + 2.0) * 0x1p-52;
+        P->gam = inc_gamma(dmax);
         return PCDM_OK;
     }
 

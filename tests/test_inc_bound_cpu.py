@@ -1,11 +1,17 @@
-"""The inequality behind the incremental ||A^T r||_inf (CPU, numpy): a
-float64 sum of the d products a_ji r_j, formed in any order, moves between
-two residuals by at most ||a_i||_1 D with
+"""The inequality behind the incremental ||A^T r||_inf (CPU): a float64 sum
+of the d products a_ji r_j, formed in any order, moves between two residuals
+by at most ||a_i||_1 D with
 D = ||r - r_old||_inf + 2 gamma max(||r||_inf, ||r_old||_inf),
 gamma = (d + 2) 2^-52 (Hoelder's inequality plus the standard bound on the
-rounding of a sum of products).  Checked on spread and concentrated changes
-of r, on residuals spanning many binades, and for the lower bound of the new
-maximum."""
+rounding of a sum of products).  D, gamma, the l1-norm factor, the moved
+column bound and the lower bound of the new maximum are taken from the
+library's own functions (inc_bound.hpp, through libpcdm_check.so), so the
+margins the kernels use are the ones checked.  Checked on spread and
+concentrated changes of r, on residuals spanning many binades, and for the
+lower bound of the new maximum."""
+
+import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -32,11 +38,31 @@ def _sum(prods, order, rng):
     return s
 
 
+_CHECK = None
+
+
+def _check():
+    global _CHECK
+    if _CHECK is None:
+        from paper_1212_0873_amd import build
+        if not os.path.exists(build.CHECK_LIB):
+            raise ImportError(f"{build.CHECK_LIB} is not built (run __graft_entry__.build())")
+        lib = ctypes.CDLL(build.CHECK_LIB)
+        d = ctypes.c_double
+        for name, nargs in (("gamma", 1), ("l1_factor", 1), ("shift", 3), ("lower", 3), ("moved", 3)):
+            fn = getattr(lib, "pcdm_check_inc_" + name)
+            fn.argtypes = [d] * nargs
+            fn.restype = d
+        _CHECK = lib
+    return _CHECK
+
+
 def _D(r, ro, d):
-    gam = (d + 2) * 2.0 ** -52
-    dlt = np.max(np.abs(r - ro)) * (1.0 + 2.0 ** -50)
-    rmax = max(np.max(np.abs(r)), np.max(np.abs(ro)))
-    return (dlt + 2.0 * gam * rmax) * (1.0 + 2.0 ** -40)
+    """D from the computed max norms, as the kernel forms it."""
+    lib = _check()
+    dlt = float(np.max(np.abs(r - ro)))
+    rmax = max(float(np.max(np.abs(r))), float(np.max(np.abs(ro))))
+    return lib.pcdm_check_inc_shift(dlt, rmax, lib.pcdm_check_inc_gamma(float(d)))
 
 
 KINDS = ["spread", "concentrated", "wide_range", "tiny_move", "aligned", "cancel_no_move"]
@@ -75,17 +101,38 @@ def test_moved_bound_holds(kind):
     elif kind == "tiny_move":
         r += 1e-15 * rng.standard_normal(m)
     D = _D(r, ro, d)
-    l1 = np.abs(vals).sum(1) * (1.0 + (d + 8) * 2.0 ** -52)
+    lib = _check()
+    # nrm_i: the float64 sum of |a_ji| times the library's factor, rounded up to float32
+    l1 = np.array([np.nextafter(np.float32(v), np.float32(np.inf)) if float(np.float32(v)) < v else np.float32(v)
+                   for v in np.abs(vals).sum(1) * lib.pcdm_check_inc_l1_factor(float(d))], dtype=np.float64)
     orders = ["seq", "rev", "pairwise", "perm"]
     s_old = np.array([_sum(vals[i] * ro[rows[i]], orders[i % 4], rng) for i in range(n)])
     s_new = np.array([_sum(vals[i] * r[rows[i]], orders[(i + 1) % 4], rng) for i in range(n)])
-    ub = np.abs(s_old) * (1.0 + 2.0 ** -40) + l1 * D
+    ub = np.array([lib.pcdm_check_inc_moved(float(u), float(w), D) for u, w in zip(np.abs(s_old), l1)])
     assert np.all(np.abs(s_new) <= ub)
-    lower = (np.max(np.abs(s_old)) - np.max(l1) * D) * (1.0 - 2.0 ** -40) - 2.0 ** -1000
+    lower = lib.pcdm_check_inc_lower(float(np.max(np.abs(s_old))), float(np.max(l1)), D)
     assert np.max(np.abs(s_new)) >= lower
     if kind == "tiny_move":
         # the bound is not vacuous: most columns are ruled out
         assert np.count_nonzero(ub >= lower) < n // 4
+
+
+def test_planted_weaker_margins_fail():
+    """The check has teeth: dropping the rounding term from D (gamma = 0)
+    breaks the bound for columns whose products cancel with no change of r."""
+    rng = np.random.default_rng(3)
+    m, n, d = 400, 300, 20
+    rows = np.stack([rng.choice(m, d, replace=False) for _ in range(n)])
+    ro = rng.standard_normal(m)
+    X = 1e3 * rng.standard_normal((n, d // 2))
+    vals = (np.concatenate([X, -X], axis=1) / ro[rows]).astype(np.float32).astype(np.float64)
+    lib = _check()
+    D0 = lib.pcdm_check_inc_shift(0.0, float(np.max(np.abs(ro))), 0.0)
+    s_a = np.array([_sum(vals[i] * ro[rows[i]], "seq", rng) for i in range(n)])
+    s_b = np.array([_sum(vals[i] * ro[rows[i]], "rev", rng) for i in range(n)])
+    l1 = np.abs(vals).sum(1)
+    weak = np.array([lib.pcdm_check_inc_moved(float(u), float(w), D0) for u, w in zip(np.abs(s_a), l1)])
+    assert np.any(np.abs(s_b) > weak)
 
 
 def test_max_norm_form_is_tighter_for_spread_changes():
