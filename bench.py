@@ -840,6 +840,8 @@ def main() -> int:
     ap.add_argument("--lanes", type=int, default=0, help="lanes per column (0 = automatic)")
     ap.add_argument("--gather-route", type=int, default=0, choices=[0, 1, 2],
                     help="partial derivatives: 0 automatic, 1 by columns, 2 by rows (option gather_route)")
+    ap.add_argument("--scatter-route", type=int, default=0, choices=[0, 1, 2],
+                    help="residual scatter: 0 automatic, 1 atomics, 2 row blocks (option scatter_route)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample length")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap run")
@@ -958,6 +960,8 @@ def main() -> int:
         p.set_option("lanes_per_column", args.lanes)
     if args.gather_route:
         p.set_option("gather_route", args.gather_route)
+    if args.scatter_route:
+        p.set_option("scatter_route", args.scatter_route)
     info = p.info()
     spe = info["refresh_every"]
     s_val = {"f32": 4, "bf16": 2, "f64": 8}[args.dtype]
@@ -1017,6 +1021,7 @@ def main() -> int:
                    "omega": info["omega"], "beta": info["beta"], "lambda": inst.lam,
                    "lanes_per_column": info["lanes_per_column"], "refresh_every": spe,
                    "gather_route": {1: "columns", 2: "rows"}[info["gather_route"]],
+                   "scatter_route": {1: "atomics", 2: "row blocks"}[info["scatter_route"]],
                    "device": dev_name},
         "roofline": {"bound": "hbm", "kernel": "k_gather", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
@@ -1025,6 +1030,8 @@ def main() -> int:
                      "measured_gbps": (traffic / gather_avg_s / 1e9) if traffic else None,
                      "measured_frac": (traffic / gather_avg_s / 1e9 / HBM_PEAK_GBPS) if traffic else None,
                      "measured_over_algorithmic": (traffic / gather_bytes) if traffic else None,
+                     "step_achieved": step_alg_bytes / t_el / 1e9,
+                     "step_frac": step_alg_bytes / t_el / 1e9 / HBM_PEAK_GBPS,
                      "copy_gbps": copy_gbps,
                      "frac_of_copy": achieved / copy_gbps,
                      "measured_frac_of_copy": (traffic / gather_avg_s / 1e9 / copy_gbps) if traffic else None,

@@ -106,7 +106,7 @@ typedef struct pcdm_info {
     int64_t narrow_below;    /* tau below which a slot gets a group of lanes      */
     int64_t nblocks;         /* blocks of a block problem (0: coordinates)        */
     int32_t loss;            /* pcdm_loss of the model (PCDM_LOSS_SQUARE: LASSO)  */
-    int32_t reserved1;
+    int32_t scatter_route;   /* residual scatter: 1 = atomics, 2 = row blocks     */
     double loss_scale;       /* model terms (see pcdm_model); lambda is l1       */
     double l2, linear, lower, upper;
     int64_t async_picks;     /* picks made by pcdm_step_async so far              */
@@ -304,6 +304,21 @@ const char *pcdm_last_error(void);
  *                      and 16, rounded up to 16).  A step whose bins overflow
  *                      is taken by route 1 instead, so results do not depend
  *                      on it;
+ *   "scatter_route"    how a step adds delta_i a_i to r: 1 = hardware float
+ *                      atomics per entry; 2 = by row blocks: the step's
+ *                      products are dealt into runs keyed by block of 4096
+ *                      rows, and one workgroup per block sums them in LDS and
+ *                      adds the sums to r with plain stores (for float32 /
+ *                      bf16 values with equal column lengths of at most 32
+ *                      entries, m <= 2^22 and tau <= 2^21; otherwise
+ *                      route 1).  Needs
+ *                      8 ceil(m/4096) ceil(tau/1024) cap + 4 ceil(m/4096)
+ *                      ceil(tau/1024) bytes.  0 (default) = 1.
+ *                      pcdm_info.scatter_route reports the route in effect;
+ *   "scatter_capacity" route 2: entries per run (0 = default: the mean count
+ *                      when every slot changes, plus seven standard
+ *                      deviations and 16, rounded up to 16); entries past it
+ *                      are added with atomics, so results do not depend on it;
  *   "reset_counters"   any value: zero nonzero_updates;
  *   "adj_tol", "adj_max_epochs", "adj_tau", "adj_check_every"
  *                      settings of pcdm_grad_backward's solve (see there);

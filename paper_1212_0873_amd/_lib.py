@@ -42,7 +42,7 @@ class pcdm_info(ctypes.Structure):
                 ("sampling", ctypes.c_int32), ("gather_route", ctypes.c_int32), ("binomial_p", ctypes.c_double),
                 ("expected_set_size", ctypes.c_double), ("mask_len", ctypes.c_int64),
                 ("narrow_below", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("loss", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32),
+                ("scatter_route", ctypes.c_int32),
                 ("loss_scale", ctypes.c_double), ("l2", ctypes.c_double), ("linear", ctypes.c_double),
                 ("lower", ctypes.c_double), ("upper", ctypes.c_double), ("async_picks", ctypes.c_int64),
                 ("async_processors", ctypes.c_int64),

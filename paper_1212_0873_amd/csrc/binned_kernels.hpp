@@ -400,3 +400,254 @@ k_bin_prox(char *__restrict__ seg, Layout lay, const typename ValT<V>::T *__rest
 }
 
 }  // namespace pcdm
+
+namespace pcdm {
+
+// --------------------------------------------------------------------------
+// Residual scatter by row blocks (option scatter_route = 2): r += delta_i a_i
+// without global atomics.  The rows are cut into blocks of 2^12; each block
+// is owned by one workgroup of k_sapply, which sums its entries in LDS and
+// adds the sums to r with plain stores.
+//
+//   k_sbin    (one workgroup per 1024 consecutive slots, as k_scatter): packs
+//             the slots with delta_i != 0; when they hold at most 2048
+//             products (late in a solve, when few coordinates still move) it
+//             adds them with atomics as k_scatter does; otherwise it reads
+//             their columns and deals the products delta_i a_ji into runs
+//             keyed by row block (LDS
+//             counting sort, then contiguous runs in the workgroup's own part
+//             of `bins`); a run that would pass its capacity adds the rest
+//             to r with atomics at once (k_sapply reads r only after this
+//             kernel has finished).  Advances the step counter.
+//   k_sapply  (one workgroup per row block): the block's runs of every
+//             k_sbin workgroup, summed per row in LDS, then added to r; it
+//             returns at once when no k_sbin workgroup made runs.
+// --------------------------------------------------------------------------
+
+constexpr int kRowBlockBits = 12;
+constexpr int kRowBlock = 1 << kRowBlockBits;
+constexpr int kSbinThreads = 256;     // k_sbin: threads, and packed columns staged at once
+constexpr int kSbinMaxBlocks = 1024;  // row blocks (m <= 2^22): 4 per k_sbin thread in its scan
+constexpr int kSbinMaxWg = 2048;      // k_sbin workgroups (tau <= 2^21)
+constexpr int kSapplyThreads = 1024;
+constexpr int kSbinDirect = 2048;  // k_sbin: at most this many products go straight to atomics
+
+struct SbinGeom {
+    int32_t nrb;   // row blocks, ceil(m / 4096)
+    int32_t nwg;   // k_sbin workgroups, ceil(tau / 1024)
+    int32_t cap;   // entries per run
+    int32_t dpad;  // entries per record (fixed-length records)
+};
+
+__host__ __device__ inline size_t sbin_lds_bytes(int nrb, int dpad)
+{
+    return (size_t)4 * nrb * sizeof(int32_t) + (size_t)kSbinThreads * dpad * (4 + 4 + 2 + 2);
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kSbinThreads)
+k_sbin(const char *__restrict__ seg, Layout lay, SbinGeom geo, typename ValT<V>::T *__restrict__ r,
+       const int32_t *__restrict__ id_slot, const typename ValT<V>::T *__restrict__ delta_slot,
+       Ctrl *__restrict__ ctrl, int64_t tau, BinEntry *__restrict__ bins, int32_t *__restrict__ counts,
+       uint32_t *__restrict__ sync)
+{
+    using T = typename ValT<V>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t s_id[kScatterSpan];
+    __shared__ T s_d[kScatterSpan];
+    __shared__ int s_cnt;
+    __shared__ int32_t s_wtot[kSbinThreads / 64];
+    const int nrb = geo.nrb, dpad = geo.dpad;
+    const int nstage = kSbinThreads * dpad;
+    int32_t *cnt = reinterpret_cast<int32_t *>(smem);
+    int32_t *offs = cnt + nrb;
+    int32_t *fill = offs + nrb;
+    int32_t *run = fill + nrb;
+    uint32_t *strow = reinterpret_cast<uint32_t *>(run + nrb);
+    float *stval = reinterpret_cast<float *>(strow + nstage);
+    uint16_t *stblk = reinterpret_cast<uint16_t *>(stval + nstage);
+    uint16_t *order = stblk + nstage;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6, gl = lane & 7, grp = lane >> 3;
+    const int64_t wg = blockIdx.x;
+    if (wg == 0 && t == 0)
+        ctrl->k += 1;  // no block of this kernel reads k
+    if (t == 0)
+        s_cnt = 0;
+    for (int q = t; q < nrb; q += kSbinThreads) {
+        cnt[q] = 0;
+        fill[q] = 0;
+        run[q] = 0;
+    }
+    __syncthreads();
+    for (int j = t; j < kScatterSpan; j += kSbinThreads) {
+        const int64_t slot = wg * kScatterSpan + j;
+        if (slot < tau) {
+            const T d = delta_slot[slot];
+            if (d != T(0)) {
+                const int q = atomicAdd(&s_cnt, 1);
+                s_id[q] = id_slot[slot];
+                s_d[q] = d;
+            }
+        }
+    }
+    __syncthreads();
+    const int npk = s_cnt;
+    if (npk * dpad <= kSbinDirect) {
+        // few changed columns (late in a solve): the plain atomic scatter of
+        // k_scatter costs less than binning them; the runs stay empty
+        const TileLanes<8> tl;
+        for (int t0 = w * 64; t0 < npk; t0 += kSbinThreads) {
+            const int e = t0 + tl.lane;
+            const bool live = e < npk;
+            const T d = live ? s_d[e] : T(0);
+            int64_t off = 0;
+            int32_t dp = 0;
+            if (live)
+                locate<V>(lay, s_id[e], off, dp);
+            tile_entries<V, 8>(seg, tl, off, dp, d, [&](int, T dq, int row, T val) {
+                if (val != T(0))
+                    atomic_add_hw<T>(r + row, dq * val);
+            });
+        }
+        for (int q = t; q < nrb; q += kSbinThreads)
+            counts[(int64_t)q * geo.nwg + wg] = 0;
+        return;
+    }
+    if (t == 0)
+        atomicOr(sync, 1u);  // k_sapply has runs to add this step
+    for (int c0 = 0; c0 < npk; c0 += kSbinThreads) {
+        // column c0 + t is packed column w * 64 + o of this chunk; its entries
+        // are read by the 8 lanes of group grp in round q (o = q * 8 + grp)
+        const int mine = c0 + t;
+        int64_t off = 0;
+        if (mine < npk)
+            off = (int64_t)s_id[mine] * lay.stride;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int o = q * 8 + grp;
+            const int sl = w * 64 + o;
+            const bool cact = c0 + sl < npk;
+            const int64_t coff = __shfl(off, o);
+            const int e = 4 * gl;
+            if (e < dpad) {
+                int rw[4] = {0, 0, 0, 0};
+                T v[4] = {T(0), T(0), T(0), T(0)};
+                T dq = T(0);
+                if (cact) {
+                    Chunk4<V>::load(seg + coff + kHeader, dpad, e, rw, v);
+                    dq = s_d[c0 + sl];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int idx = sl * dpad + e + u;
+                    if (cact && v[u] != T(0)) {
+                        const uint32_t row = (uint32_t)rw[u];
+                        const int blk = (int)(row >> kRowBlockBits);
+                        strow[idx] = row & (kRowBlock - 1);
+                        stval[idx] = (float)(dq * v[u]);
+                        stblk[idx] = (uint16_t)blk;
+                        atomicAdd(&cnt[blk], 1);
+                    } else {
+                        stblk[idx] = 0xFFFFu;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int q = t; q < nrb; q += kSbinThreads)
+            offs[q] = cnt[q];
+        __syncthreads();
+        const int32_t nvalid = block_exclusive_scan4(offs, nrb, s_wtot);  // ends with a barrier
+        for (int idx = t; idx < nstage; idx += kSbinThreads) {
+            const uint16_t blk = stblk[idx];
+            if (blk != 0xFFFFu)
+                order[offs[blk] + atomicAdd(&fill[blk], 1)] = (uint16_t)idx;
+        }
+        __syncthreads();
+        for (int j = t; j < nvalid; j += kSbinThreads) {
+            const int idx = order[j];
+            const int blk = stblk[idx];
+            const int pos = run[blk] + (j - offs[blk]);
+            if (pos < geo.cap) {
+                BinEntry be;
+                be.key = strow[idx];
+                be.val = stval[idx];
+                bins[((int64_t)blk * geo.nwg + wg) * geo.cap + pos] = be;
+            } else {
+                // past the run's capacity: straight into r (k_sapply runs later)
+                atomic_add_hw<T>(r + (((uint32_t)blk << kRowBlockBits) | strow[idx]), (T)stval[idx]);
+            }
+        }
+        __syncthreads();
+        for (int q = t; q < nrb; q += kSbinThreads) {
+            run[q] += cnt[q];
+            cnt[q] = 0;
+            fill[q] = 0;
+        }
+        __syncthreads();
+    }
+    for (int q = t; q < nrb; q += kSbinThreads)
+        counts[(int64_t)q * geo.nwg + wg] = run[q] < geo.cap ? run[q] : geo.cap;
+}
+
+// Row block b = blockIdx.x: the sums of its entries over every k_sbin
+// workgroup, added to r[4096 b ..].
+template <typename T>
+__global__ void __launch_bounds__(kSapplyThreads)
+k_sapply(const BinEntry *__restrict__ bins, const int32_t *__restrict__ counts, SbinGeom geo, int64_t m,
+         T *__restrict__ r, uint32_t *__restrict__ sync)
+{
+    __shared__ T acc[kRowBlock];
+    __shared__ int32_t pre[kSbinMaxWg + 1];
+    __shared__ int32_t s_wtot[kSapplyThreads / 64];
+    const int t = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int nwg = geo.nwg;
+    // sync[0] != 0: some k_sbin workgroup made runs this step; sync[1] counts
+    // the blocks of this kernel that are done; the last one resets both for
+    // the next step (every other block has read sync[0] before counting)
+    const bool any = __hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (!any) {
+        if (t == 0 && atomicAdd(sync + 1, 1u) == gridDim.x - 1) {
+            sync[0] = 0u;
+            sync[1] = 0u;
+        }
+        return;
+    }
+    for (int j = t; j < kRowBlock; j += kSapplyThreads)
+        acc[j] = T(0);
+    for (int q = t; q < nwg; q += kSapplyThreads)
+        pre[q] = counts[b * nwg + q];
+    __syncthreads();
+    const int32_t total = block_exclusive_scan4(pre, nwg, s_wtot);
+    if (t == 0)
+        pre[nwg] = total;
+    __syncthreads();
+    for (int32_t j = t; j < total; j += kSapplyThreads) {
+        int lo = 0, hi = nwg;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= j)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BinEntry be = bins[(b * nwg + lo) * geo.cap + (j - pre[lo])];
+        atomicAdd(&acc[be.key], (T)be.val);
+    }
+    __syncthreads();
+    for (int j = t; j < kRowBlock; j += kSapplyThreads) {
+        const int64_t row = (b << kRowBlockBits) + j;
+        const T a = acc[j];
+        if (row < m && a != T(0))
+            r[row] += a;
+    }
+    if (t == 0 && atomicAdd(sync + 1, 1u) == gridDim.x - 1) {
+        sync[0] = 0u;
+        sync[1] = 0u;
+    }
+}
+
+}  // namespace pcdm

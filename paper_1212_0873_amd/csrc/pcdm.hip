@@ -206,6 +206,16 @@ struct pcdm_problem {
     void *bhdr = nullptr;     // [tau] {x_i, 1/L_i}
     void *bpart = nullptr;    // [8 * tau] working type
     uint32_t *bover = nullptr;  // [2] overflow flags by step parity
+
+    // residual scatter by row blocks (binned_kernels.hpp)
+    int scatter_route = 0;     // option: 0 automatic, 1 atomics, 2 row blocks where eligible
+    bool srows = false;        // route in effect
+    int64_t sbin_cap_opt = 0;  // option: entries per run (0 = from the expected count)
+    SbinGeom sgeo{};
+    int64_t sbin_tau = 0;
+    void *sbins = nullptr;     // [nrb * ceil(tau/1024) * cap] BinEntry
+    int32_t *scounts = nullptr;
+    uint32_t *ssync = nullptr;  // [2] runs-made flag, k_sapply blocks done
 };
 
 namespace {
@@ -249,7 +259,7 @@ void free_problem(pcdm_problem *P)
     void *bufs[] = {P->seg, P->pc, P->x, P->r, P->r64, P->b64, P->id_slot,
                     P->delta_slot, P->ctrl, P->nz_part, P->part, P->part2, P->mask, P->claim, P->bp, P->invlb, P->dx,
                     P->t32, P->ub, P->rold, P->nrm, P->inc, P->cnt, P->bins, P->bcounts, P->bhdr, P->bpart,
-                    P->bover};
+                    P->bover, P->sbins, P->scounts, P->ssync};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -564,12 +574,118 @@ int route_update(pcdm_problem *P)
     return PCDM_OK;
 }
 
+void free_sbins(pcdm_problem *P)
+{
+    if (P->sbins)
+        (void)hipFree(P->sbins);
+    if (P->scounts)
+        (void)hipFree(P->scounts);
+    if (P->ssync)
+        (void)hipFree(P->ssync);
+    P->sbins = nullptr;
+    P->scounts = nullptr;
+    P->ssync = nullptr;
+    P->sbin_tau = 0;
+}
+
+// Whether the row-block scatter can take this problem's steps, and why not.
+const char *sbin_ineligible(const pcdm_problem *P)
+{
+    if (P->group)
+        return "the row-block scatter is built for coordinates";
+    if (P->dtype == PCDM_F64)
+        return "the row-block scatter takes float32 or bf16 values";
+    if (P->lay.fixed_dpad < 1 || P->lay.fixed_dpad > kBinMaxDpad)
+        return "the row-block scatter needs equal column lengths of at most 32 entries";
+    if (ceil_div(P->m, kRowBlock) > kSbinMaxBlocks)
+        return "too many rows for the row-block scatter (at most 2^22)";
+    if (ceil_div(P->tau, kScatterSpan) > kSbinMaxWg)
+        return "tau too large for the row-block scatter (at most 2^21)";
+    return nullptr;
+}
+
+// Decide the scatter route and size its buffers (API calls only).
+int sroute_update(pcdm_problem *P)
+{
+    const bool ok = sbin_ineligible(P) == nullptr;
+    const bool want = P->scatter_route == 2;
+    if (!(ok && want)) {
+        P->srows = false;
+        free_sbins(P);
+        return PCDM_OK;
+    }
+    SbinGeom g;
+    g.nrb = (int32_t)ceil_div(P->m, kRowBlock);
+    g.nwg = (int32_t)ceil_div(P->tau, kScatterSpan);
+    g.dpad = (int32_t)P->lay.fixed_dpad;
+    if (P->sbin_cap_opt > 0) {
+        g.cap = (int32_t)P->sbin_cap_opt;
+    } else {
+        // mean count of a run when every slot changes and rows are uniform, plus 7 standard deviations
+        const double mu = (double)kScatterSpan * g.dpad / g.nrb;
+        g.cap = (int32_t)(16 * ceil_div((int64_t)std::ceil(mu + 7.0 * std::sqrt(mu) + 16.0), 16));
+    }
+    if (P->sbins && P->sbin_tau == P->tau && P->sgeo.nrb == g.nrb && P->sgeo.cap == g.cap &&
+        P->sgeo.dpad == g.dpad) {
+        P->srows = true;
+        return PCDM_OK;
+    }
+    free_sbins(P);
+    P->srows = false;
+    const size_t lds = sbin_lds_bytes(g.nrb, g.dpad);
+    hipError_t e = hipMalloc(&P->sbins, (size_t)g.nrb * g.nwg * g.cap * sizeof(BinEntry));
+    if (e == hipSuccess)
+        e = hipMalloc(&P->scounts, (size_t)g.nrb * g.nwg * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&P->ssync, 2 * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemset(P->ssync, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = P->dtype == PCDM_BF16
+                ? hipFuncSetAttribute((const void *)k_sbin<bf16s>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                : hipFuncSetAttribute((const void *)k_sbin<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+        free_sbins(P);
+        (void)hipGetLastError();
+        return hip_fail(e, "row-block scatter set-up");
+    }
+    P->sgeo = g;
+    P->sbin_tau = P->tau;
+    P->srows = true;
+    return PCDM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Per value type operations.
 // ---------------------------------------------------------------------------
 
 template <typename V> struct Ops {
     using T = typename ValT<V>::T;
+
+    // The residual scatter of a step over 64-slot tiles: hardware atomics
+    // (k_scatter), or row blocks (k_sbin, k_sapply).
+    template <int G> static void launch_scatter(pcdm_problem *P, hipStream_t s)
+    {
+        hipEvent_t t1 = clock_start(P, s);
+        if constexpr (!std::is_same<V, double>::value) {
+            if (P->srows && P->sbins && P->sbin_tau == P->tau) {
+                const SbinGeom geo = P->sgeo;
+                hipLaunchKernelGGL((k_sbin<V>), dim3((unsigned)geo.nwg), dim3(kSbinThreads),
+                                   sbin_lds_bytes(geo.nrb, geo.dpad), s, (const char *)P->seg, P->lay, geo, (T *)P->r,
+                                   (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl, P->tau,
+                                   (BinEntry *)P->sbins, P->scounts, P->ssync);
+                hipLaunchKernelGGL((k_sapply<T>), dim3((unsigned)geo.nrb), dim3(kSapplyThreads), 0, s,
+                                   (const BinEntry *)P->sbins, (const int32_t *)P->scounts, geo, P->m, (T *)P->r,
+                                   P->ssync);
+                clock_stop(P, CLK_SCATTER, t1, s);
+                return;
+            }
+        }
+        const int sgrid = grid_for(P->tau, kScatterSpan, P->nblk_max);
+        hipLaunchKernelGGL((k_scatter<V, G>), dim3(sgrid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
+                           (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl, P->tau);
+        clock_stop(P, CLK_SCATTER, t1, s);
+    }
 
     // Partial derivatives by rows (k_bin, k_bin_dot, k_bin_prox), then the scatter.
     template <int G, int C> static void launch_binned(pcdm_problem *P, hipStream_t s)
@@ -590,11 +706,7 @@ template <typename V> struct Ops {
                            (uint32_t)P->n, 1.0 / P->beta, prox_params(P), (const v2d_t *)P->bhdr,
                            (const T *)P->bpart, P->bover);
         clock_stop(P, CLK_GATHER, t0, s);
-        const int sgrid = grid_for(P->tau, kScatterSpan, P->nblk_max);
-        hipEvent_t t1 = clock_start(P, s);
-        hipLaunchKernelGGL((k_scatter<V, G>), dim3(sgrid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
-                           (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl, P->tau);
-        clock_stop(P, CLK_SCATTER, t1, s);
+        launch_scatter<G>(P, s);
     }
 
     template <int G, int C, int Loss> static void launch_step(pcdm_problem *P, hipStream_t s)
@@ -613,6 +725,10 @@ template <typename V> struct Ops {
                                (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part, P->seed,
                                P->tau, (uint32_t)P->n, 1.0 / P->beta, prox_params(P), slot_plan(P));
             clock_stop(P, CLK_GATHER, t0, s);
+            if (P->srows && P->sbins && P->sbin_tau == P->tau) {
+                launch_scatter<G>(P, s);
+                return;
+            }
             hipEvent_t t1 = clock_start(P, s);
             hipLaunchKernelGGL((k_scatter_narrow<V, G>), dim3(grid), dim3(kBlock), 0, s, (const char *)P->seg,
                                P->lay, (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl,
@@ -626,12 +742,7 @@ template <typename V> struct Ops {
                            (const T *)P->r, P->x, P->id_slot, (T *)P->delta_slot, P->ctrl, P->nz_part,
                            P->seed, P->tau, (uint32_t)P->n, 1.0 / P->beta, prox_params(P), slot_plan(P));
         clock_stop(P, CLK_GATHER, t0, s);
-        const int sgrid = grid_for(P->tau, kScatterSpan, P->nblk_max);
-        hipEvent_t t1 = clock_start(P, s);
-        hipLaunchKernelGGL((k_scatter<V, G>), dim3(sgrid), dim3(kBlock), 0, s, (const char *)P->seg, P->lay,
-                           (T *)P->r, (const int32_t *)P->id_slot, (const T *)P->delta_slot, P->ctrl,
-                           P->tau);
-        clock_stop(P, CLK_SCATTER, t1, s);
+        launch_scatter<G>(P, s);
     }
 
     // One call of the asynchronous variant: `picks` picks over P processors
@@ -1316,6 +1427,7 @@ int create_impl(const pcdm_csc *A, const double *b, double lambda, int64_t tau, 
         P->atb_inf = hc.scal[3];
     }
     PCDM_TRY(route_update(P));
+    PCDM_TRY(sroute_update(P));
     guard.p = nullptr;
     *out = P;
     return PCDM_OK;
@@ -1363,6 +1475,12 @@ std::vector<unsigned char> step_signature(const pcdm_problem *P)
     put(P->bgeo.cap);
     put(P->bgeo.ns);
     put(P->bin_tau);
+    put(P->srows);
+    put(P->sbins);
+    put(P->scounts);
+    put(P->ssync);
+    put(P->sgeo.cap);
+    put(P->sbin_tau);
     return sig;
 }
 
@@ -1560,6 +1678,7 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         h->tau = t;
         compute_beta(h);
         PCDM_TRY(route_update(h));
+        PCDM_TRY(sroute_update(h));
     } else if (k == "lanes_per_column" || k == "chunks_per_lane") {
         const int v = (int)value;
         if ((double)v != value || v < 0)
@@ -1659,6 +1778,23 @@ int pcdm_set_option(pcdm_problem *h, const char *key, double value)
         HIP_TRY(hipStreamSynchronize(h->last_stream));
         h->bin_cap_opt = (int64_t)value;
         PCDM_TRY(route_update(h));
+    } else if (k == "scatter_route") {
+        if (value != 0.0 && value != 1.0 && value != 2.0)
+            return fail(PCDM_EINVAL, "scatter_route must be 0 (automatic), 1 (atomics) or 2 (row blocks)");
+        if (value == 2.0) {
+            const char *why = sbin_ineligible(h);
+            if (why)
+                return fail(PCDM_EINVAL, why);
+        }
+        HIP_TRY(hipStreamSynchronize(h->last_stream));
+        h->scatter_route = (int)value;
+        PCDM_TRY(sroute_update(h));
+    } else if (k == "scatter_capacity") {
+        if (!(value >= 0.0) || value > 65536.0 || value != std::floor(value))
+            return fail(PCDM_EINVAL, "scatter_capacity must be an integer in [0, 65536]");
+        HIP_TRY(hipStreamSynchronize(h->last_stream));
+        h->sbin_cap_opt = (int64_t)value;
+        PCDM_TRY(sroute_update(h));
     } else if (k == "reset_counters") {
         hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(kBlock), 0, h->last_stream, h->nz_part,
                            (uint64_t)0, (int64_t)h->nblk_max);
@@ -1698,6 +1834,7 @@ int pcdm_get_info(pcdm_problem *h, pcdm_info *out)
     out->chunks_per_lane = h->chunks;
     out->sampling = h->sampling;
     out->gather_route = h->binned ? 2 : 1;
+    out->scatter_route = h->srows ? 2 : 1;
     out->binomial_p = h->pb;
     out->expected_set_size = expected_set_size(h);
     out->mask_len = h->mask_len;

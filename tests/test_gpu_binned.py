@@ -122,3 +122,99 @@ def test_binned_route_eligibility(pc):
         assert p.info()["gather_route"] == 2
         p.set_option("gather_route", 1)
         assert p.info()["gather_route"] == 1
+
+
+# --------------------------------------------------------------------------- #
+# residual scatter by row blocks (option scatter_route = 2)
+# --------------------------------------------------------------------------- #
+
+def _run_s(pc, inst, tau, rounds, steps, cap=0, graph_steps=32, seed=5, gather_route=1, narrow=None):
+    ref = oracle.Solver(inst.A, inst.b, inst.lam, tau=tau, seed=seed)
+    with pc.Problem(inst.A, inst.b, inst.lam, tau, seed=seed) as p:
+        p.set_option("scatter_route", 2)
+        p.set_option("gather_route", gather_route)
+        if cap:
+            p.set_option("scatter_capacity", cap)
+        if narrow is not None:
+            p.set_option("narrow_below", narrow)
+        p.set_option("graph_steps", graph_steps)
+        assert p.info()["scatter_route"] == 2
+        worst = 0.0
+        for rnd in range(rounds):
+            p.step(steps)
+            ref.step(steps)
+            F, _ = p.objective()
+            Fr = ref.objective()
+            worst = max(worst, abs(F - Fr) / abs(Fr))
+            assert F == pytest.approx(Fr, rel=1e-5), rnd
+        x = p.get_x()
+        r_lib = p.get_residual()
+        nz = p.info()["nonzero_updates"]
+    xerr = np.max(np.abs(x - ref.x)) / max(np.max(np.abs(ref.x)), 1e-300)
+    _say(f"  worst rel F {worst:.2e}, x err {xerr:.2e} of max|x|, {nz} nonzero updates")
+    assert xerr <= 1e-5
+    return r_lib
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_row_block_scatter_ragged_tau(pc, dtype):
+    """1e6 rows (245 blocks of 4096), tau = 50,001: a partial last packing
+    workgroup and a partial last row block."""
+    inst = _instance(1_000_000, 200_000, 20, 11, dtype)
+    _run_s(pc, inst, 50_001, rounds=4, steps=3)
+
+
+def test_row_block_scatter_tiny_rows_graphs(pc):
+    """m = 5000 (two row blocks), tau = n, graph replays of 8 steps."""
+    inst = _instance(5000, 3000, 12, 12, "f32", balanced=False)
+    _run_s(pc, inst, 3000, rounds=3, steps=20, graph_steps=8)
+
+
+def test_row_block_scatter_overflow_goes_to_atomics(pc):
+    """Capacity 1 per run: almost every product is added with an atomic in
+    the packing kernel; the trajectory is unchanged."""
+    inst = _instance(300_000, 60_000, 20, 13, "f32")
+    _run_s(pc, inst, 20_000, rounds=3, steps=3, cap=1)
+
+
+def test_row_block_scatter_with_rows_gather_and_narrow_layout(pc):
+    """Both routes by rows together; then the lane-group layout of small tau."""
+    inst = _instance(2_500_000, 60_000, 20, 14, "f32")
+    _run_s(pc, inst, 20_000, rounds=3, steps=2, gather_route=2)
+    inst = _instance(100_000, 30_000, 20, 15, "f32")
+    _run_s(pc, inst, 1000, rounds=3, steps=30, narrow=10**9)
+
+
+def test_row_block_scatter_keeps_the_residual(pc):
+    """Over several epochs (float64 refreshes in between) the maintained r
+    stays the residual of the iterate: r = A x - b to float32 accuracy."""
+    import scipy.sparse as sp
+    inst = _instance(1_000_000, 100_000, 20, 16, "f32")
+    rng = np.random.default_rng(0)
+    with pc.Problem(inst.A, inst.b, inst.lam, 16384, seed=1) as p:
+        p.set_option("scatter_route", 2)
+        p.set_option("refresh_every", 0)  # no refresh: r is only what the scatters made it
+        p.step(25)
+        x = p.get_x()
+        r = p.get_residual()
+    M = sp.csc_matrix((inst.A.values_f64(), inst.A.row_idx, inst.A.col_ptr), shape=(inst.A.m, inst.A.n))
+    want = M @ x - inst.b
+    err = np.max(np.abs(r - want)) / np.max(np.abs(inst.b))
+    _say(f"  drift of r after 25 steps without refresh: {err:.2e} of max|b|")
+    assert err <= 1e-5
+
+
+def test_row_block_scatter_eligibility(pc):
+    inst = _instance(2000, 1000, 8, 17, "f64")
+    with pc.Problem(inst.A, inst.b, inst.lam, 64, seed=0) as p:
+        assert p.info()["scatter_route"] == 1
+        with pytest.raises(pc.PCDMError, match="float32 or bf16"):
+            p.set_option("scatter_route", 2)
+    inst = _instance(2000, 1000, 8, 18, "f32")
+    with pc.Problem(inst.A, inst.b, inst.lam, 64, seed=0) as p:
+        p.set_option("scatter_route", 2)
+        assert p.info()["scatter_route"] == 2
+        p.set_option("tau", 500)
+        assert p.info()["scatter_route"] == 2
+        p.set_option("scatter_route", 1)
+        assert p.info()["scatter_route"] == 1
