@@ -140,26 +140,19 @@ def big_cpu_baseline(cfg: dict, dtype: str, host: dict, tau: int, seconds: float
                       f"also not timed)"}
 
 
-def time_to_gap(p, spe: int, target: float, limit_s: float, check_every: int = 5) -> dict:
+def gap_check(args):
+    return "auto" if args.gap_check == "auto" else int(args.gap_check)
+
+
+def time_to_gap(p, target: float, limit_s: float, check_every="auto") -> dict:
     """Wall time from the handle's current state until the certified float64
-    duality gap (F - D)/D <= target, checking every `check_every` epochs (the
-    gap evaluations are inside the timed region)."""
-    import torch
-    torch.cuda.synchronize()
-    t_g = time.perf_counter()
-    epochs = 0
-    rel = float("inf")
-    F = gap = None
-    while time.perf_counter() - t_g < limit_s:
-        p.step(check_every * spe)
-        epochs += check_every
-        F, gap = p.objective(gap=True)
-        rel = gap / max(abs(F - gap), 1e-300)
-        if rel <= target:
-            break
-    tt = time.perf_counter() - t_g
-    return {"target_rel_gap": target, "reached": bool(rel <= target), "seconds": tt, "epochs": epochs,
-            "rel_gap": rel, "F": F, "check_every_epochs": check_every, "includes_gap_evaluations": True}
+    duality gap (F - D)/D <= target (``Problem.solve``: gap evaluations inside
+    the timed region, every `check_every` epochs or on the cost-aware
+    schedule "auto")."""
+    st = p.solve(rel_gap=target, check_every=check_every, max_seconds=limit_s)
+    return {"target_rel_gap": target, "reached": bool(st["converged"]), "seconds": st["seconds"],
+            "epochs": st["epochs"], "rel_gap": st["rel_gap"], "F": st["F"], "check_every_epochs": check_every,
+            "gap_evaluations": st["checks"], "includes_gap_evaluations": True}
 
 
 def run_batched(args) -> int:
@@ -197,7 +190,7 @@ def run_batched(args) -> int:
         with pc.Problem(A, b, lam, tau, seed=j) as p:
             p.set_option("lanes_per_column", sched["lanes_per_column"])
             p.set_option("chunks_per_lane", sched["chunks_per_lane"])
-            r = time_to_gap(p, -(-A.n // tau), 1e-6, args.gap_seconds)
+            r = time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))
         seq_t += r["seconds"]
         seq_ok &= r["reached"]
     out = {"metric": METRIC, "mode": "batched", "value": upd_b / tb, "unit": "coord updates/s",
@@ -228,7 +221,7 @@ def run_dtypes(args) -> int:
     for dt in ("f64", "f32", "bf16"):
         A = inst.A.astype(dt) if dt != "f64" else inst.A
         with pc.Problem(A, inst.b, inst.lam, tau, seed=0) as p:
-            r = time_to_gap(p, -(-A.n // tau), 1e-6, args.gap_seconds)
+            r = time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))
             res[dt] = r
         del A
         print(f"[bench] {dt}: {r}", file=sys.stderr, flush=True)
@@ -408,7 +401,7 @@ def run_taus(args) -> int:
                 r["epoch_steps"] = inf["refresh_every"]
                 r["gather_alg_gbps"] = b_gather * tau / (r["gather_avg_us"] * 1e-6) / 1e9
                 p.set_x(np.zeros(A.n), k=0)
-                r["time_to_gap"] = time_to_gap(p, inf["refresh_every"], 1e-6, args.gap_seconds)
+                r["time_to_gap"] = time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))
                 res[str(tau)] = r
                 print(f"[bench] {cfg} tau={tau}: {r}", file=sys.stderr, flush=True)
             omega = p.info()["omega"]
@@ -450,7 +443,7 @@ def run_samplings(args) -> int:
             r["distinct_updates_per_s"] = r["slot_updates_per_s"] * es / tau
             r["beta"] = inf["beta"]
             p.set_x(np.zeros(A.n), k=0)
-            r["time_to_gap"] = time_to_gap(p, inf["refresh_every"], 1e-6, args.gap_seconds)
+            r["time_to_gap"] = time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))
             res[name] = r
             print(f"[bench] {name}: {r}", file=sys.stderr, flush=True)
     out = {"metric": METRIC, "mode": "samplings", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
@@ -499,7 +492,7 @@ def run_async(args) -> int:
             p.set_option("tau", tau)
             p.set_option("refresh_every", -(-A.n // tau))
             p.set_x(np.zeros(A.n), k=0)
-            sync = time_to_gap(p, -(-A.n // tau), 1e-6, args.gap_seconds)
+            sync = time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))
             r_tau = {"beta": p.info()["beta"], "sync_time_to_gap": sync}
             for label, reads, rounds in (("default", -1, 4), ("cached_r1", 0, 1), ("cached_r4", 0, 4),
                                          ("acquire", 1, 0), ("atomic", 2, 0)):
@@ -514,7 +507,7 @@ def run_async(args) -> int:
                 rate = 2 * A.n / (time.perf_counter() - t0)
                 p.set_x(np.zeros(A.n), k=0)
                 r_tau[label] = {"picks_per_s": rate, "processors": p.info()["async_processors"],
-                                "time_to_gap": async_time_to_gap(p, 1e-6, args.gap_seconds)}
+                                "time_to_gap": async_time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))}
                 print(f"[bench] async tau={tau} {label}: {r_tau[label]}", file=sys.stderr, flush=True)
             res[str(tau)] = r_tau
     out = {"metric": METRIC, "mode": "async", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
@@ -702,7 +695,7 @@ def run_group(args) -> int:
     ns, sms = p.kernel_time("scatter")
     p.set_option("kernel_timing", 0)
     p.set_x(np.zeros(A.n), k=0)
-    ttg = time_to_gap(p, spe, 1e-6, args.gap_seconds)
+    ttg = time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))
     p.close()
     out = {"metric": METRIC, "mode": "group", "n_gpus": 1, "dtype": args.dtype, "data": "synthetic",
            "config": {"workload": "group_lasso_1e6x1e7_d20_blocks4", "nblocks": inf["nblocks"], "tau_blocks": tau,
@@ -737,7 +730,7 @@ def run_adjoint(args) -> int:
         with pc.Problem(inst.A, inst.b, inst.lam, 4096, seed=2) as p:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st = p.solve(rel_gap=1e-6, check_every=5)
+            st = p.solve(rel_gap=1e-6)
             torch.cuda.synchronize()
             t_fwd = time.perf_counter() - t0
             x = p.get_x()
@@ -846,6 +839,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap run")
     ap.add_argument("--gap-seconds", type=float, default=60.0)
+    ap.add_argument("--gap-check", default="auto",
+                    help='epochs between duality-gap evaluations in the time-to-gap runs, or "auto"')
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "dtypes", "taus", "samplings", "async", "models", "path", "group",
@@ -1049,7 +1044,7 @@ def main() -> int:
     if not args.no_gap:
         # time to a certified 1e-6 relative gap from x = 0 (float64 duality gap)
         p.set_x(np.zeros(A.n), k=0)
-        out["time_to_gap"] = time_to_gap(p, spe, 1e-6, args.gap_seconds)
+        out["time_to_gap"] = time_to_gap(p, 1e-6, args.gap_seconds, gap_check(args))
         print(f"[bench] {out['time_to_gap']}", file=sys.stderr, flush=True)
     p.close()
     del p

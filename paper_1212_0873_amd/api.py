@@ -260,23 +260,46 @@ class Problem:
             bb = b.to(_torch().float64).contiguous()
             check(self._lib.pcdm_set_rhs(self._h, bb.data_ptr(), 1, current_stream()))
 
-    def solve(self, rel_gap: float = 1e-6, check_every: int = 5, max_epochs: int = 100000) -> dict:
+    def solve(self, rel_gap: float = 1e-6, check_every="auto", max_epochs: int = 100000,
+              max_seconds: Optional[float] = None) -> dict:
         """Step until the certified duality gap (F - D)/D <= rel_gap; returns
-        {"epochs", "F", "gap", "rel_gap", "converged"}."""
+        {"epochs", "F", "gap", "rel_gap", "converged", "checks", "seconds"}.
+
+        ``check_every``: epochs between gap evaluations, or "auto" for
+        :func:`next_check_interval` on the measured cost of the last
+        evaluation and of the epochs before it.  ``max_seconds`` bounds the
+        wall time (checked at evaluations)."""
+        import time
+        auto = isinstance(check_every, str) and check_every == "auto"
+        interval = 1 if auto else int(check_every)
+        if interval < 1:
+            raise ValueError("check_every must be >= 1 or 'auto'")
         inf = self.info()
         spe = -(-(inf["nblocks"] or self.n) // inf["tau"])  # one epoch: every coordinate or block once
-        epochs = 0
+        sync = _torch().cuda.current_stream().synchronize if auto else (lambda: None)
+        epochs = checks = 0
         F = gap = None
         rel = float("inf")
+        sync()
+        t0 = t_prev = time.perf_counter()
         while epochs < max_epochs:
-            self.step(check_every * spe)
-            epochs += check_every
+            n_ep = min(interval, max_epochs - epochs)
+            self.step(n_ep * spe)
+            epochs += n_ep
+            sync()
+            t_mid = time.perf_counter()
             F, gap = self.objective(gap=True)
+            checks += 1
+            t_end = time.perf_counter()
             D = F - gap
             rel = gap / max(abs(D), 1e-300)
-            if rel <= rel_gap:
+            if rel <= rel_gap or (max_seconds is not None and t_end - t0 >= max_seconds):
                 break
-        return {"epochs": epochs, "F": F, "gap": gap, "rel_gap": rel, "converged": rel <= rel_gap}
+            if auto:
+                interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / n_ep, epochs)
+            t_prev = t_end
+        return {"epochs": epochs, "F": F, "gap": gap, "rel_gap": rel, "converged": rel <= rel_gap,
+                "checks": checks, "seconds": time.perf_counter() - t0}
 
     def solve_path(self, lambdas, rel_gap: float = 1e-6, check_every: int = 1, max_epochs: int = 100000,
                    keep_x: bool = True) -> list:
@@ -298,6 +321,26 @@ class Problem:
                 st["x"] = self.get_x()
             out.append(st)
         return out
+
+
+def next_check_interval(check_seconds: float, epoch_seconds: float, epochs_done: int = 0,
+                        share: float = 0.1, cap: int = 16) -> int:
+    """Epochs until the next duality-gap evaluation, between 1 and ``cap``.
+
+    Checking every I epochs costs c/I per epoch (c: one evaluation, e: one
+    epoch) and runs on average I/2 epochs past the first one that meets the
+    target; with about as many epochs left as done (E), I = sqrt(2 E c / e)
+    balances the two.  While E is small that rule would evaluate often, and an
+    evaluation needs max_i |a_i^T r|: a pass over all of A costing about an
+    epoch while many coordinates move, far less once the iterate settles (the
+    bounded route).  So the interval is also at least what keeps the last
+    evaluation near ``share`` of the stepping time: coarse early, every epoch
+    near the solution when evaluations are cheap there."""
+    if not (epoch_seconds > 0.0) or not (check_seconds >= 0.0):
+        return 1
+    by_share = -(-check_seconds // (share * epoch_seconds))
+    by_overshoot = round((2.0 * max(epochs_done, 0) * check_seconds / epoch_seconds) ** 0.5)
+    return int(max(1, min(cap, max(by_share, by_overshoot))))
 
 
 def sample(seed: int, k: int, tau: int, n: int):

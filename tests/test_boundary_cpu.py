@@ -185,3 +185,24 @@ def test_every_option_key_is_documented():
     documented = set(re.findall(r'"([a-z_0-9]+)"', block))
     assert accepted == documented, (accepted - documented, documented - accepted)
 
+
+
+def test_gap_check_schedule():
+    """Host logic of Problem.solve's "auto" schedule: the interval keeps the
+    last evaluation's cost near a tenth of the stepping time and balances
+    evaluation cost against the expected overshoot, within [1, 16]."""
+    from paper_1212_0873_amd.api import next_check_interval as nci
+    assert nci(0.0002, 0.00164, 300) == 9     # sqrt(2 * 300 * 0.2 / 1.64) = 8.55
+    assert nci(0.0002, 0.00164, 0) == 2       # share term alone
+    assert nci(0.0063, 0.211, 22) == 1        # sqrt(1.31) rounds to 1
+    assert nci(0.0063, 0.211, 200) == 3
+    assert nci(0.2, 0.2, 10**6) == 16
+    assert nci(0.200, 0.211) == 10        # a full pass over A costs about an epoch
+    assert nci(0.0063, 0.211) == 1        # the bounded route near the solution
+    assert nci(0.0, 0.2) == 1
+    assert nci(5.0, 0.01) == 16           # capped
+    assert nci(0.03, 0.1, share=0.5) == 1
+    assert nci(0.031, 0.1, share=0.1) == 4
+    assert nci(1.0, 0.0) == 1 and nci(float("nan"), 1.0) == 1 and nci(1.0, float("nan")) == 1
+    with pytest.raises(ValueError):
+        pc.Problem.solve(object.__new__(pc.Problem), check_every=0)

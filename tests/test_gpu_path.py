@@ -50,3 +50,26 @@ def test_path_matches_oracle_at_every_lambda(pc):
             cold += p.solve(rel_gap=1e-10, check_every=1)["epochs"]
     print(f"path epochs warm {warm} vs cold {cold}", flush=True)
     assert warm < cold
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_auto_gap_schedule_certifies_and_keeps_the_trajectory(pc, dtype):
+    """solve(check_every="auto") stops at a point whose gap, recomputed by the
+    oracle from the returned x, meets the target; the gap evaluations do not
+    touch the iterate, so the same number of steps without any evaluation
+    reaches the same F."""
+    inst = make_config("small_2000x1000", dtype=dtype)
+    target = 1e-9 if dtype == "f64" else 1e-6
+    with pc.Problem(inst.A, inst.b, inst.lam, 8, seed=0) as p:
+        st = p.solve(rel_gap=target)
+        x = p.get_x()
+    assert st["converged"] and st["checks"] >= 1 and st["seconds"] > 0
+    gap, F, D = oracle.dual_gap(inst.A, inst.b, x, inst.lam)
+    assert gap / abs(D) <= target * 1.01, (gap / abs(D), st)
+    assert st["F"] == pytest.approx(F, rel=1e-10)  # both float64 at the same x
+    spe = -(-inst.A.n // 8)
+    with pc.Problem(inst.A, inst.b, inst.lam, 8, seed=0) as q:
+        q.step(st["epochs"] * spe)
+        Fq, _ = q.objective()
+    assert Fq == pytest.approx(st["F"], rel=1e-12 if dtype == "f64" else 1e-6)
+    print(f"  {dtype}: {st['epochs']} epochs, {st['checks']} gap evaluations", flush=True)
