@@ -274,8 +274,8 @@ def random_gather_ceiling(m: int, nthreads: int = 1_000_000, reps: int = 20) -> 
     stream = torch.cuda.current_stream()
     sptr = ctypes.c_void_p(stream.cuda_stream)
 
-    def launch(salt):
-        rc = lib.pcdm_calib_random_gather(table.data_ptr(), m, nthreads, salt, out.data_ptr(), sptr)
+    def launch(salt, rows=m):
+        rc = lib.pcdm_calib_random_gather(table.data_ptr(), rows, nthreads, salt, out.data_ptr(), sptr)
         if rc != 0:
             raise RuntimeError(f"pcdm_calib_random_gather failed: {rc}")
 
@@ -301,11 +301,18 @@ def random_gather_ceiling(m: int, nthreads: int = 1_000_000, reps: int = 20) -> 
 
     dt = timed(launch)
     dta = timed(launch_atomic)
+    # the same reads on smaller tables: one that each XCD's 4 MB L2 holds whole,
+    # and one beyond the L2s but inside the 256 MB Infinity Cache
+    by_size = {}
+    for small in (1 << 19, 1 << 24):
+        if small < m:
+            by_size[4 * small] = nthreads * reads / timed(lambda salt: launch(salt, small))
     del table, out
     torch.cuda.empty_cache()
     return {"table_bytes": 4 * m, "reads_per_launch": nthreads * reads, "avg_launch_us": dt * 1e6,
             "reads_per_s": nthreads * reads / dt, "atomic_avg_launch_us": dta * 1e6,
-            "atomics_per_s": nthreads * reads / dta}
+            "atomics_per_s": nthreads * reads / dta,
+            "reads_per_s_smaller_tables": {f"{b >> 20} MiB": v for b, v in by_size.items()}}
 
 
 def read_l2_counters(kernel: str, workload: str, dtype: str, tau: int) -> Optional[dict]:
