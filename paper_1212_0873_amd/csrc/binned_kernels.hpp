@@ -148,13 +148,17 @@ __device__ __forceinline__ int32_t block_exclusive_scan4(int32_t *v, int cnt, in
 
 // Binning: workgroup a takes slots [1024 a, 1024 a + 1024) of step k in two
 // halves of 512.  Writes id_slot, hdr (x_i, 1/L_i) per slot, the runs of its
-// sub-bins and their counts; sets over[k & 1] if a sub-bin overflows.
+// sub-bins and their counts; sets over[k & 1] if a sub-bin overflows.  The
+// entries of the second half are loaded (into the registers the first half's
+// entries have left) before the first half is sorted and written, so their
+// HBM latency overlaps that work.
 template <typename V>
 __global__ void __launch_bounds__(kBinHalf)
 k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restrict__ ctrl, uint64_t seed,
       int64_t tau, uint32_t n, int32_t *__restrict__ id_slot, v2d_t *__restrict__ hdr,
       BinEntry *__restrict__ bins, int32_t *__restrict__ counts, uint32_t *__restrict__ over)
 {
+    using VT = typename ValT<V>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_keys[kNiceRounds];
     __shared__ int32_t s_wtot[kBinHalf / 64];
@@ -171,6 +175,7 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
 
     const int t = threadIdx.x;
     const int lane = t & 63, w = t >> 6, gl = lane & 7, grp = lane >> 3;
+    const int e = 4 * gl;  // this lane's 4-entry chunk of each column it reads
     const int64_t a = blockIdx.x;
     for (int q = t; q < ns; q += kBinHalf) {
         cnt[q] = 0;
@@ -179,45 +184,72 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     }
     const uint64_t k = ctrl->k;
     const NiceKey key = nice_key_block(seed, k, n, s_keys);  // synchronises the block
-    bool overflow = false;
-    for (int h = 0; h < 2; ++h) {
-        const int64_t slot = a * kBinSlotsA + (int64_t)h * kBinHalf + t;
-        const bool act = slot < tau;
+
+    // entries of one half: in round q the 8 lanes of group grp read column
+    // q * 8 + grp of this wave, one 4-entry chunk each (dpad <= 32).  The
+    // loads are unconditional (an idle lane reads column 0's first chunk,
+    // always present, and ignores it): loads under a branch would make the
+    // compiler wait for each round's data before issuing the next round.
+    int rw[8][4];
+    VT v[8][4];
+    bool cact[8];
+    bool hact = false;
+    int64_t hslot = 0;
+    uint32_t hid = 0;
+    v2d_t hv;
+    auto load_half = [&](int h) {
+        hslot = a * kBinSlotsA + (int64_t)h * kBinHalf + t;
+        hact = hslot < tau;
         int64_t off = 0;
-        if (act) {
-            const uint32_t i = nice_slot((uint32_t)slot, key);
-            id_slot[slot] = (int32_t)i;
-            off = (int64_t)i * lay.stride;
-            hdr[slot] = ld_rec(reinterpret_cast<const v2d_t *>(seg + off));
+        hid = 0;
+        if (hact) {
+            hid = nice_slot((uint32_t)hslot, key);
+            off = (int64_t)hid * lay.stride;
         }
-        // entries: in round q the 8 lanes of group grp read column q * 8 + grp
-        // of this wave, one 4-entry chunk each (dpad <= 32); unrolled so that
-        // the loads of all rounds are in flight together
+        hv = ld_rec(reinterpret_cast<const v2d_t *>(seg + off));
+        const int el = e < dpad ? e : 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int o = q * 8 + grp;
             const int64_t coff = __shfl(off, o);
-            const bool cact = __shfl((int)act, o) != 0;
-            const int sl = w * 64 + o;  // staged column within the half
-            const int e = 4 * gl;
+            cact[q] = __shfl((int)hact, o) != 0 && e < dpad;
+            Chunk4<V>::load(seg + coff + kHeader, dpad, el, rw[q], v[q]);
+        }
+    };
+    // the slot's coordinate and record header, stored once the half's loads
+    // are all in flight
+    auto store_half = [&]() {
+        if (hact) {
+            id_slot[hslot] = (int32_t)hid;
+            hdr[hslot] = hv;
+        }
+    };
+
+    bool overflow = false;
+    load_half(0);
+    // unrolled: the second half's loads land in the registers its staging
+    // reads, with no copies across a loop edge that would wait for them
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        store_half();
+        // stage this half's entries in LDS, keyed and counted by sub-bin
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int sl = w * 64 + q * 8 + grp;  // staged column within the half
             if (e < dpad) {
-                int rw[4] = {0, 0, 0, 0};
-                typename ValT<V>::T v[4] = {0, 0, 0, 0};
-                if (cact)
-                    Chunk4<V>::load(seg + coff + kHeader, dpad, e, rw, v);
                 // slot of column sl within its k_bin_dot block
                 const uint32_t sblk =
                     (uint32_t)(((a * kBinSlotsA + (int64_t)h * kBinHalf + sl)) & (int64_t)(kBinBlock - 1));
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int idx = sl * dpad + e + u;
-                    if (cact && v[u] != 0) {
-                        const uint32_t row = (uint32_t)rw[u];
+                    if (cact[q] && v[q][u] != VT(0)) {
+                        const uint32_t row = (uint32_t)rw[q][u];
                         const uint32_t xr = (uint32_t)(row / (uint64_t)geo.rx);
                         const uint32_t within = row - (uint32_t)((uint64_t)xr * (uint64_t)geo.rx);
                         const int sub = (int)(xr * (uint32_t)geo.nw + (within >> kBinWinBits));
                         stkey[idx] = (sblk << kBinWinBits) | (within & kBinWinMask);
-                        stval[idx] = (float)v[u];
+                        stval[idx] = (float)v[q][u];
                         stsub[idx] = (uint16_t)sub;
                         atomicAdd(&cnt[sub], 1);
                     } else {
@@ -226,6 +258,8 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
                 }
             }
         }
+        if (h == 0)
+            load_half(1);  // in flight while this half is sorted and written
         __syncthreads();
         block_exclusive_scan(cnt, offs, ns, s_wtot);  // ends with a barrier
         const int nvalid = offs[ns - 1] + cnt[ns - 1];
@@ -268,11 +302,10 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
 // block) as one flat list of entries, 512 at a time (one per thread): every
 // block of a range then moves through the range's rows at the same pace, so
 // the rows in use at any moment (about 1.3 MB for the 64 blocks of an XCD)
-// stay in that XCD's L2.  The entries of the next stretch are loaded before
-// r is read for the current one, so the two latencies overlap.  (Measured on
-// the 2e8-row instance: 1024 entries per block at a time, or two windows per
-// stage taken by each wave on its own, let the blocks drift apart and L2
-// misses rose from 8.0e6 to 1.3e7-1.6e7 per launch.)
+// stay in that XCD's L2.  (Measured on the 2e8-row instance: 1024 entries
+// per block at a time, or two windows per stage taken by each wave on its
+// own, let the blocks drift apart and L2 misses rose from 8.0e6 to
+// 1.3e7-1.6e7 per launch.)
 constexpr int kBinPerBlock = kBinBlock / kBinSlotsA;  // k_bin workgroups per block (16)
 constexpr int kBinMaxRuns = (kBinMaxSub / kBinRanges) * kBinPerBlock;
 
@@ -328,6 +361,13 @@ k_bin_dot(const BinEntry *__restrict__ bins, const int32_t *__restrict__ counts,
     if (t == 0)
         pre[nruns] = total;
     __syncthreads();
+    // one entry per thread at a time; the next stretch's entry is looked up
+    // and loaded after r is read for the current one.  The load sits under a
+    // branch, so the compiler drains it before the next read of r: each
+    // stretch costs an entry load and a read of r in turn, and that common
+    // pace keeps the blocks of a range on the same rows (prefetching the
+    // entries two stretches ahead, branch-free, let the blocks drift apart:
+    // 325 us per launch with twice the L2 misses, 1.6e7)
     BinEntry cur{0u, 0.0f};
     uint32_t rowb = 0;
     if (t < total)
