@@ -63,8 +63,8 @@ def test_scaled_recipe_matches_oracle(pc):
 
 
 # --------------------------------------------------------------------------- #
-# the full 2e8 x 5e8 instance (1e10 nonzeros), float32, tau = 2^20: the
-# launch configuration the benchmark times
+# the full 2e8 x 5e8 instance (1e10 nonzeros), tau = 2^20, float32 values (the
+# launch configuration the benchmark times) and bf16 values
 # --------------------------------------------------------------------------- #
 
 BIG = dict(m=200_000_000, n=500_000_000, d=20, K=100_000, sigma=0.01, seed=0)
@@ -72,25 +72,25 @@ BIG_TAU = 1 << 20
 CHUNK = 1 << 22
 
 
-def _host_pass(out):
+def _host_pass(out, dtype):
     """b, omega and ||A^T b||_inf of the whole instance on the host: every
-    column regenerated from the recipe (threads), the statistics by the
-    oracle.  Runs beside the device work."""
+    column regenerated from the recipe (threads) with the stored values of
+    the dtype, the statistics by the oracle.  Runs beside the device work."""
     try:
         m, n, d, K, sigma, seed = (BIG[k] for k in ("m", "n", "d", "K", "sigma", "seed"))
-        b = biggen.host_b(seed, m, n, d, K, sigma, "f32")
+        b = biggen.host_b(seed, m, n, d, K, sigma, dtype)
         st = oracle.ColumnStats(m, b)
         for i0 in range(0, n, CHUNK):
             cnt = min(CHUNK, n - i0)
-            cp, rows, vals = biggen.host_columns(seed, m, n, d, i0, cnt, "f32")
+            cp, rows, vals = biggen.host_columns(seed, m, n, d, i0, cnt, dtype)
             st.add(cp, rows, vals)
         out["b"], out["stats"] = b, st
     except BaseException as e:  # reported by the test that joins
         out["error"] = e
 
 
-@pytest.fixture(scope="module")
-def big(pc):
+@pytest.fixture(scope="module", params=["f32", "bf16"])
+def big(pc, request):
     """The instance generated on the device and handed to the library (its
     own omega, beta and ||A^T b||_inf; lambda = 0.05 ||A^T b||_inf from the
     library's value), with the host pass running beside it."""
@@ -98,14 +98,15 @@ def big(pc):
     import time
 
     import torch
+    dtype = request.param
     host = {}
-    th = threading.Thread(target=_host_pass, args=(host,), daemon=True)
+    th = threading.Thread(target=_host_pass, args=(host, dtype), daemon=True)
     t0 = time.time()
     th.start()
     m, n, d, K, sigma, seed = (BIG[k] for k in ("m", "n", "d", "K", "sigma", "seed"))
-    A, b, _ = biggen.device_instance(m, n, d, K, sigma, seed=seed, dtype="f32")
+    A, b, _ = biggen.device_instance(m, n, d, K, sigma, seed=seed, dtype=dtype)
     torch.cuda.synchronize()
-    _say(f"generated 1e10 entries on the device ({time.time() - t0:.0f} s)")
+    _say(f"generated 1e10 {dtype} entries on the device ({time.time() - t0:.0f} s)")
     p = pc.Problem(A, b, 1.0, BIG_TAU, seed=seed)
     del A, b
     torch.cuda.empty_cache()
@@ -114,7 +115,7 @@ def big(pc):
     _say(f"created ({time.time() - t0:.0f} s): omega {inf['omega']}, beta {inf['beta']:.6f}, "
          f"||A^T b||_inf {inf['atb_inf']:.15e}, gather route {inf['gather_route']}")
     assert inf["gather_route"] == 1  # plain gather by default
-    yield {"p": p, "host": host, "thread": th, "t0": t0}
+    yield {"p": p, "host": host, "thread": th, "t0": t0, "dtype": dtype}
     p.close()
     torch.cuda.empty_cache()
 
@@ -166,7 +167,7 @@ def test_full_size_three_steps_match_oracle(big):
     touched = np.zeros(0, dtype=np.int64)
     for k in range(3):
         S = np.sort(oracle.sample_nice(seed, k, BIG_TAU, n).astype(np.int64))
-        cp, rows, vals = biggen.host_column_list(seed, m, n, d, S, "f32")
+        cp, rows, vals = biggen.host_column_list(seed, m, n, d, S, big["dtype"])
         if k == 0:
             g = ref.gradient(S, cp, rows, vals)
             # float32 r = fl32(-b) and float32 sums of d products: |error| <=
