@@ -146,9 +146,10 @@ def test_full_size_create_matches_host_pass(big):
     assert inf["beta"] == pytest.approx(oracle.beta_nice(st.omega, BIG_TAU, BIG["n"]), rel=1e-15)
 
 
-def test_full_size_three_steps_match_oracle(big):
+def test_full_size_steps_match_oracle(big):
     """Three steps of tau = 2^20 at 1e10 nonzeros (the second one with the
-    partial derivatives taken by rows): after every step F (float64
+    partial derivatives taken by rows), then three of tau = 2^16 (the
+    lane-group layout) from the state they reach: after every step F (float64
     refresh on the device) against the oracle's F on its own float64 r and x,
     every coordinate of S_k against the oracle's, coordinates outside every
     S_k still 0, and the count of nonzero updates of step 0 (from x = 0 a
@@ -162,11 +163,16 @@ def test_full_size_three_steps_match_oracle(big):
     host = _host(big)
     st = host["stats"]
     lam = 0.05 * st.atb_inf
-    beta = oracle.beta_nice(st.omega, BIG_TAU, n)
-    ref = oracle.ColumnSetSolver(m, n, host["b"], lam, beta)
+    ref = oracle.ColumnSetSolver(m, n, host["b"], lam, oracle.beta_nice(st.omega, BIG_TAU, n))
     touched = np.zeros(0, dtype=np.int64)
-    for k in range(3):
-        S = np.sort(oracle.sample_nice(seed, k, BIG_TAU, n).astype(np.int64))
+    # (step, tau, gather route)
+    plan = [(0, BIG_TAU, 1), (1, BIG_TAU, 2), (2, BIG_TAU, 1), (3, 1 << 16, 1), (4, 1 << 16, 1), (5, 1 << 16, 1)]
+    for k, tau, route in plan:
+        if tau != p.info()["tau"]:
+            p.set_option("tau", tau)
+            ref.beta = oracle.beta_nice(st.omega, tau, n)
+            assert p.info()["beta"] == pytest.approx(ref.beta, rel=1e-15)
+        S = np.sort(oracle.sample_nice(seed, k, tau, n).astype(np.int64))
         cp, rows, vals = biggen.host_column_list(seed, m, n, d, S, big["dtype"])
         if k == 0:
             g = ref.gradient(S, cp, rows, vals)
@@ -175,9 +181,8 @@ def test_full_size_three_steps_match_oracle(big):
             absdot = np.add.reduceat(np.abs(vals) * np.abs(ref.r[rows]), cp[:-1])
             edge = int(np.count_nonzero(np.abs(np.abs(g) - lam) <= (d + 3) * 2.0 ** -24 * absdot))
         changed = ref.step_with_columns(S, cp, rows, vals)
-        # step 1 takes the partial derivatives by rows (option gather_route 2)
-        p.set_option("gather_route", 2 if k == 1 else 1)
-        assert p.info()["gather_route"] == (2 if k == 1 else 1)
+        p.set_option("gather_route", route)
+        assert p.info()["gather_route"] == route
         p.step(1)
         if k == 0:
             got = p.info()["nonzero_updates"]
@@ -193,7 +198,7 @@ def test_full_size_three_steps_match_oracle(big):
         del x
         want_x = ref.x[S]
         xerr = np.max(np.abs(got_x - want_x)) / max(np.max(np.abs(ref.x)), 1e-300)
-        _say(f"step {k}: F {F:.12e} vs oracle {F_ref:.12e} (rel {abs(F - F_ref) / F_ref:.2e}); "
+        _say(f"step {k} (tau {tau}): F {F:.12e} vs oracle {F_ref:.12e} (rel {abs(F - F_ref) / F_ref:.2e}); "
              f"x on S_k max err {xerr:.2e} of max|x|; {np.count_nonzero(want_x)} nonzero on S_k")
         assert F == pytest.approx(F_ref, rel=1e-5)
         assert xerr <= 1e-5
