@@ -394,6 +394,27 @@ def test_full_size_steps_match_oracle(pc, c2_full):
         _say(f"nonzero updates after 3 steps: gpu {p.info()['nonzero_updates']} oracle {ref.changed}")
 
 
+@pytest.mark.parametrize("tau,steps", [(65536, 24), (1024, 400)])
+def test_full_size_small_tau_matches_oracle(pc, c2_full, tau, steps):
+    """The instance's other two tau (the lane-group layout): F after every
+    quarter of the run and every x_i at the end against the oracle on the
+    same float32-stored matrix, with the same beta."""
+    inst = c2_full
+    ref = oracle.Solver(inst.A, inst.b, inst.lam, tau=tau, seed=1)
+    with pc.Problem(inst.A, inst.b, inst.lam, tau, seed=1) as p:
+        info = p.info()
+        assert info["beta"] == pytest.approx(ref.beta, rel=1e-15)
+        for q in range(4):
+            p.step(steps // 4)
+            ref.step(steps // 4)
+            F, _ = p.objective()
+            Fr = ref.objective()
+            _say(f"tau {tau} after {(q + 1) * steps // 4} steps: F {F:.9e} oracle {Fr:.9e}")
+            assert abs(F - Fr) <= 1e-5 * abs(Fr)
+        x = p.get_x()
+        assert np.max(np.abs(x - ref.x)) <= 1e-5 * np.max(np.abs(ref.x))
+
+
 # --------------------------------------------------------------------------- #
 # the two step-kernel layouts (64-slot tiles, a lane group per slot)
 # --------------------------------------------------------------------------- #
