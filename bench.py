@@ -155,6 +155,35 @@ def time_to_gap(p, target: float, limit_s: float, check_every="auto") -> dict:
             "gap_evaluations": st["checks"], "includes_gap_evaluations": True}
 
 
+def oracle_time_to_gap(A, b, lam, tau: int, target: float, limit_s: float) -> dict:
+    """The float64 oracle on one core from x = 0 until its certified gap
+    (F - D)/D <= target, with the gap evaluations on the schedule the GPU
+    solve uses (from the measured cost of the last evaluation and of the
+    epochs before it); for instances small enough to solve on the host."""
+    import oracle
+    from paper_1212_0873_amd.api import next_check_interval
+    ref = oracle.Solver(A, b, lam, tau=tau, seed=0)
+    spe = ref.steps_per_epoch()
+    epochs = checks = 0
+    interval = 1
+    rel = float("inf")
+    t0 = t_prev = time.perf_counter()
+    while time.perf_counter() - t0 < limit_s:
+        ref.step(interval * spe)
+        epochs += interval
+        t_mid = time.perf_counter()
+        gap, F, D = ref.gap()
+        checks += 1
+        t_end = time.perf_counter()
+        rel = gap / max(abs(D), 1e-300)
+        if rel <= target:
+            break
+        interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / interval, epochs)
+        t_prev = t_end
+    return {"target_rel_gap": target, "reached": bool(rel <= target), "seconds": time.perf_counter() - t0,
+            "epochs": epochs, "gap_evaluations": checks, "rel_gap": rel, "cores": 1}
+
+
 def run_batched(args) -> int:
     """The batched path: `count` uneven LASSO problems on a lambda grid, all
     solved to a certified 1e-6 gap in one batch (graph-replayed steps) vs the
@@ -1071,6 +1100,9 @@ def main() -> int:
                                "kind": "oracle", "cpu_model": cpu_model(), "host_threads_available": os.cpu_count(),
                                "sample": f"{steps} steps of tau={tau} from x=0 on the same matrix "
                                          f"({steps * tau} updates, {tc:.1f} s, float64, one thread)"}
+        if A.nnz <= 2_000_000 and not args.no_gap:
+            out["cpu_baseline"]["time_to_gap"] = oracle_time_to_gap(A, inst.b, inst.lam, tau, 1e-6,
+                                                                    args.gap_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
