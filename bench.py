@@ -246,6 +246,7 @@ def run_dtypes(args) -> int:
     torch.cuda.set_device(0)
     inst = make_config(args.config, dtype="f64", tau=args.tau)
     tau = min(args.tau, inst.A.n)
+    print(f"[bench] generated {args.config} (nnz {inst.A.nnz})", file=sys.stderr, flush=True)
     res = {}
     for dt in ("f64", "f32", "bf16"):
         A = inst.A.astype(dt) if dt != "f64" else inst.A
@@ -863,8 +864,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--config", default="lasso_2e8x5e8", choices=sorted(WORKLOAD_NAMES))
-    ap.add_argument("--tau", type=int, default=1 << 20)
+    ap.add_argument("--config", default=None, choices=sorted(WORKLOAD_NAMES),
+                    help="workload (default: lasso_2e8x5e8 in the single mode, lasso_1e6x1e7 in the "
+                         "dtypes, samplings and async modes)")
+    ap.add_argument("--tau", type=int, default=None,
+                    help="default: 2^20 on lasso_2e8x5e8, 1e6 on the other workloads")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--lanes", type=int, default=0, help="lanes per column (0 = automatic)")
     ap.add_argument("--gather-route", type=int, default=0, choices=[0, 1, 2],
@@ -899,6 +903,17 @@ def main() -> int:
                "MI355X here; multi-GPU sharding is a design note, not a built path")
         if int(os.environ.get("RANK", "0")) == 0:
             print(msg, file=sys.stderr)
+        return 2
+
+    from workloads.configs import CONFIGS
+    host_modes = ("dtypes", "samplings", "async")
+    if args.config is None:
+        args.config = "lasso_1e6x1e7" if args.mode in host_modes else "lasso_2e8x5e8"
+    if args.tau is None:
+        args.tau = 1 << 20 if args.config == "lasso_2e8x5e8" else 1_000_000
+    if args.mode in host_modes and CONFIGS[args.config].get("device_gen"):
+        print(f"--mode {args.mode} builds its instance on the host; {args.config} is generated on the "
+              f"device only (use the single mode)", file=sys.stderr)
         return 2
 
     if args.mode == "batched":
