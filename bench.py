@@ -489,25 +489,37 @@ def run_samplings(args) -> int:
     return 0
 
 
-def async_time_to_gap(p, target: float, limit_s: float, check_every: int = 5) -> dict:
+def async_time_to_gap(p, target: float, limit_s: float, check_every="auto") -> dict:
     """Wall time of asynchronous epochs (n picks each, float64 refresh after
     each) until the certified gap (F - D)/D <= target, checked every
-    `check_every` epochs (inside the timed region)."""
+    `check_every` epochs or on the cost-aware schedule of the synchronous
+    solve ("auto"); the evaluations are inside the timed region."""
     import torch
+
+    from paper_1212_0873_amd.api import next_check_interval
+    auto = check_every == "auto"
+    interval = 1 if auto else int(check_every)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    epochs = 0
+    t0 = t_prev = time.perf_counter()
+    epochs = checks = 0
     rel = float("inf")
     F = None
     while time.perf_counter() - t0 < limit_s:
-        p.step_async(check_every)
-        epochs += check_every
+        p.step_async(interval)
+        epochs += interval
+        torch.cuda.synchronize()
+        t_mid = time.perf_counter()
         F, gap = p.objective(gap=True)
+        checks += 1
+        t_end = time.perf_counter()
         rel = gap / max(abs(F - gap), 1e-300)
         if rel <= target:
             break
+        if auto:
+            interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / interval, epochs)
+        t_prev = t_end
     return {"target_rel_gap": target, "reached": bool(rel <= target), "seconds": time.perf_counter() - t0,
-            "epochs": epochs, "rel_gap": rel, "F": F, "check_every_epochs": check_every}
+            "epochs": epochs, "rel_gap": rel, "F": F, "check_every_epochs": check_every, "gap_evaluations": checks}
 
 
 def run_async(args) -> int:
