@@ -167,6 +167,7 @@ def oracle_time_to_gap(A, b, lam, tau: int, target: float, limit_s: float) -> di
     epochs = checks = 0
     interval = 1
     rel = float("inf")
+    last = None
     t0 = t_prev = time.perf_counter()
     while time.perf_counter() - t0 < limit_s:
         ref.step(interval * spe)
@@ -178,7 +179,10 @@ def oracle_time_to_gap(A, b, lam, tau: int, target: float, limit_s: float) -> di
         rel = gap / max(abs(D), 1e-300)
         if rel <= target:
             break
-        interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / interval, epochs)
+        trend = (last, (epochs, rel)) if last is not None else None
+        interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / interval, epochs, trend=trend,
+                                       target=target)
+        last = (epochs, rel)
         t_prev = t_end
     return {"target_rel_gap": target, "reached": bool(rel <= target), "seconds": time.perf_counter() - t0,
             "epochs": epochs, "gap_evaluations": checks, "rel_gap": rel, "cores": 1}
@@ -504,6 +508,7 @@ def async_time_to_gap(p, target: float, limit_s: float, check_every="auto") -> d
     epochs = checks = 0
     rel = float("inf")
     F = None
+    last = None
     while time.perf_counter() - t0 < limit_s:
         p.step_async(interval)
         epochs += interval
@@ -516,7 +521,10 @@ def async_time_to_gap(p, target: float, limit_s: float, check_every="auto") -> d
         if rel <= target:
             break
         if auto:
-            interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / interval, epochs)
+            trend = (last, (epochs, rel)) if last is not None else None
+            interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / interval, epochs, trend=trend,
+                                           target=target)
+            last = (epochs, rel)
         t_prev = t_end
     return {"target_rel_gap": target, "reached": bool(rel <= target), "seconds": time.perf_counter() - t0,
             "epochs": epochs, "rel_gap": rel, "F": F, "check_every_epochs": check_every, "gap_evaluations": checks}

@@ -8,6 +8,7 @@ stream, and raises :class:`PCDMError` on a negative status.
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Optional
 
 import numpy as np
@@ -280,6 +281,7 @@ class Problem:
         epochs = checks = 0
         F = gap = None
         rel = float("inf")
+        last = None  # (epochs, rel_gap) of the previous evaluation
         sync()
         t0 = t_prev = time.perf_counter()
         while epochs < max_epochs:
@@ -296,7 +298,10 @@ class Problem:
             if rel <= rel_gap or (max_seconds is not None and t_end - t0 >= max_seconds):
                 break
             if auto:
-                interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / n_ep, epochs)
+                trend = (last, (epochs, rel)) if last is not None else None
+                interval = next_check_interval(t_end - t_mid, (t_mid - t_prev) / n_ep, epochs,
+                                               trend=trend, target=rel_gap)
+                last = (epochs, rel)
             t_prev = t_end
         return {"epochs": epochs, "F": F, "gap": gap, "rel_gap": rel, "converged": rel <= rel_gap,
                 "checks": checks, "seconds": time.perf_counter() - t0}
@@ -324,7 +329,7 @@ class Problem:
 
 
 def next_check_interval(check_seconds: float, epoch_seconds: float, epochs_done: int = 0,
-                        share: float = 0.1, cap: int = 16) -> int:
+                        share: float = 0.1, cap: int = 16, trend=None, target: float = 0.0) -> int:
     """Epochs until the next duality-gap evaluation, between 1 and ``cap``.
 
     Checking every I epochs costs c/I per epoch (c: one evaluation, e: one
@@ -335,12 +340,23 @@ def next_check_interval(check_seconds: float, epoch_seconds: float, epochs_done:
     epoch while many coordinates move, far less once the iterate settles (the
     bounded route).  So the interval is also at least what keeps the last
     evaluation near ``share`` of the stepping time: coarse early, every epoch
-    near the solution when evaluations are cheap there."""
+    near the solution when evaluations are cheap there.  ``trend`` =
+    ((epochs, rel_gap) of the previous evaluation, (epochs, rel_gap) of the
+    last): when the gap fell, the interval is at most 0.8 of the epochs its
+    geometric rate needs to reach ``target``, so that a coarse interval does
+    not run far past the target."""
     if not (epoch_seconds > 0.0) or not (check_seconds >= 0.0):
         return 1
     by_share = -(-check_seconds // (share * epoch_seconds))
     by_overshoot = round((2.0 * max(epochs_done, 0) * check_seconds / epoch_seconds) ** 0.5)
-    return int(max(1, min(cap, max(by_share, by_overshoot))))
+    interval = int(max(1, min(cap, max(by_share, by_overshoot))))
+    if trend is not None and target > 0.0:
+        (e0, g0), (e1, g1) = trend
+        if e1 > e0 and 0.0 < g1 < g0 and g1 > target:
+            rate = math.log(g1 / g0) / (e1 - e0)  # < 0: log-gap per epoch
+            need = math.log(target / g1) / rate   # epochs to the target at that rate
+            interval = max(1, min(interval, math.floor(0.8 * need)))
+    return interval
 
 
 def sample(seed: int, k: int, tau: int, n: int):

@@ -204,5 +204,10 @@ def test_gap_check_schedule():
     assert nci(0.03, 0.1, share=0.5) == 1
     assert nci(0.031, 0.1, share=0.1) == 4
     assert nci(1.0, 0.0) == 1 and nci(float("nan"), 1.0) == 1 and nci(1.0, float("nan")) == 1
+    # a falling gap caps the interval at 0.8 of the epochs its rate needs:
+    # 5.2 -> 1.47e-3 over 10 epochs is 0.44 per epoch, 8.9 epochs to 1e-6
+    assert nci(0.19, 0.211, 22, trend=((12, 5.2), (22, 1.47e-3)), target=1e-6) == 7
+    assert nci(0.19, 0.211, 22, trend=((12, 1e-3), (22, 2e-3)), target=1e-6) == 10   # rising: no cap
+    assert nci(0.19, 0.211, 22, trend=((12, 5.2), (22, 1.1e-6)), target=1e-6) == 1   # almost there
     with pytest.raises(ValueError):
         pc.Problem.solve(object.__new__(pc.Problem), check_every=0)
