@@ -152,7 +152,8 @@ def time_to_gap(p, target: float, limit_s: float, check_every="auto") -> dict:
     st = p.solve(rel_gap=target, check_every=check_every, max_seconds=limit_s)
     return {"target_rel_gap": target, "reached": bool(st["converged"]), "seconds": st["seconds"],
             "epochs": st["epochs"], "rel_gap": st["rel_gap"], "F": st["F"], "check_every_epochs": check_every,
-            "gap_evaluations": st["checks"], "includes_gap_evaluations": True}
+            "gap_evaluations": st["checks"], "includes_gap_evaluations": True,
+            "evaluated_at": [(e, float(f"{g:.3g}"), round(c * 1e3, 1)) for e, g, c in st["evaluations"]]}
 
 
 def oracle_time_to_gap(A, b, lam, tau: int, target: float, limit_s: float) -> dict:

@@ -264,7 +264,8 @@ class Problem:
     def solve(self, rel_gap: float = 1e-6, check_every="auto", max_epochs: int = 100000,
               max_seconds: Optional[float] = None) -> dict:
         """Step until the certified duality gap (F - D)/D <= rel_gap; returns
-        {"epochs", "F", "gap", "rel_gap", "converged", "checks", "seconds"}.
+        {"epochs", "F", "gap", "rel_gap", "converged", "checks", "seconds",
+        "evaluations": [(epochs, rel_gap, seconds of the evaluation), ...]}.
 
         ``check_every``: epochs between gap evaluations, or "auto" for
         :func:`next_check_interval` on the measured cost of the last
@@ -282,6 +283,7 @@ class Problem:
         F = gap = None
         rel = float("inf")
         last = None  # (epochs, rel_gap) of the previous evaluation
+        evals = []
         sync()
         t0 = t_prev = time.perf_counter()
         while epochs < max_epochs:
@@ -295,6 +297,7 @@ class Problem:
             t_end = time.perf_counter()
             D = F - gap
             rel = gap / max(abs(D), 1e-300)
+            evals.append((epochs, rel, t_end - t_mid))
             if rel <= rel_gap or (max_seconds is not None and t_end - t0 >= max_seconds):
                 break
             if auto:
@@ -304,7 +307,7 @@ class Problem:
                 last = (epochs, rel)
             t_prev = t_end
         return {"epochs": epochs, "F": F, "gap": gap, "rel_gap": rel, "converged": rel <= rel_gap,
-                "checks": checks, "seconds": time.perf_counter() - t0}
+                "checks": checks, "seconds": time.perf_counter() - t0, "evaluations": evals}
 
     def solve_path(self, lambdas, rel_gap: float = 1e-6, check_every: int = 1, max_epochs: int = 100000,
                    keep_x: bool = True) -> list:
