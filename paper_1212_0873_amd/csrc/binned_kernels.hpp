@@ -66,7 +66,7 @@ struct BinEntry {
 };
 
 // Dynamic LDS of k_bin: four counters per sub-bin, then per staged entry its
-// key, value, sub-bin and a sorted-order index.
+// key and value (one 8-byte pair), sub-bin and a sorted-order index.
 __host__ __device__ inline size_t bin_lds_bytes(int ns, int dpad)
 {
     return (size_t)4 * ns * sizeof(int32_t) + (size_t)kBinHalf * dpad * (4 + 4 + 2 + 2);
@@ -168,9 +168,8 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     int32_t *offs = cnt + ns;
     int32_t *fill = offs + ns;
     int32_t *run = fill + ns;
-    uint32_t *stkey = reinterpret_cast<uint32_t *>(run + ns);
-    float *stval = reinterpret_cast<float *>(stkey + nstage);
-    uint16_t *stsub = reinterpret_cast<uint16_t *>(stval + nstage);
+    uint2 *stkv = reinterpret_cast<uint2 *>(run + ns);  // (key, value bits) of each staged entry
+    uint16_t *stsub = reinterpret_cast<uint16_t *>(stkv + nstage);
     uint16_t *order = stsub + nstage;
 
     const int t = threadIdx.x;
@@ -226,6 +225,7 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     };
 
     bool overflow = false;
+    const double inv_rx = 1.0 / (double)geo.rx;
     load_half(0);
     // unrolled: the second half's loads land in the registers its staging
     // reads, with no copies across a loop edge that would wait for them
@@ -240,22 +240,44 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
                 // slot of column sl within its k_bin_dot block
                 const uint32_t sblk =
                     (uint32_t)(((a * kBinSlotsA + (int64_t)h * kBinHalf + sl)) & (int64_t)(kBinBlock - 1));
+                uint32_t kk[4];
+                float vv[4];
+                uint16_t ss[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int idx = sl * dpad + e + u;
+                    kk[u] = 0u;
+                    vv[u] = 0.0f;
+                    ss[u] = 0xFFFFu;
                     if (cact[q] && v[q][u] != VT(0)) {
                         const uint32_t row = (uint32_t)rw[q][u];
-                        const uint32_t xr = (uint32_t)(row / (uint64_t)geo.rx);
-                        const uint32_t within = row - (uint32_t)((uint64_t)xr * (uint64_t)geo.rx);
+                        // row range xr = floor(row / rx): the float64 quotient is
+                        // within one of it, and one comparison each way fixes it
+                        uint32_t xr = (uint32_t)((double)row * inv_rx);
+                        int64_t lo = (int64_t)xr * geo.rx;
+                        if (lo > (int64_t)row) {
+                            xr -= 1u;
+                            lo -= geo.rx;
+                        } else if (lo + geo.rx <= (int64_t)row) {
+                            xr += 1u;
+                            lo += geo.rx;
+                        }
+                        const uint32_t within = row - (uint32_t)lo;
                         const int sub = (int)(xr * (uint32_t)geo.nw + (within >> kBinWinBits));
-                        stkey[idx] = (sblk << kBinWinBits) | (within & kBinWinMask);
-                        stval[idx] = (float)v[q][u];
-                        stsub[idx] = (uint16_t)sub;
+                        kk[u] = (sblk << kBinWinBits) | (within & kBinWinMask);
+                        vv[u] = (float)v[q][u];
+                        ss[u] = (uint16_t)sub;
                         atomicAdd(&cnt[sub], 1);
-                    } else {
-                        stsub[idx] = 0xFFFFu;
                     }
                 }
+                // two 16-byte LDS stores of (key, value) pairs and one 8-byte
+                // store of sub-bins: padded column lengths are multiples of 4,
+                // so idx is too
+                const int idx = sl * dpad + e;
+                *reinterpret_cast<uint4 *>(stkv + idx) =
+                    make_uint4(kk[0], __float_as_uint(vv[0]), kk[1], __float_as_uint(vv[1]));
+                *reinterpret_cast<uint4 *>(stkv + idx + 2) =
+                    make_uint4(kk[2], __float_as_uint(vv[2]), kk[3], __float_as_uint(vv[3]));
+                *reinterpret_cast<ushort4 *>(stsub + idx) = make_ushort4(ss[0], ss[1], ss[2], ss[3]);
             }
         }
         if (h == 0)
@@ -269,14 +291,19 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
                 order[offs[sub] + atomicAdd(&fill[sub], 1)] = (uint16_t)idx;
         }
         __syncthreads();
+        // offs[q] becomes the place in the sub-bin's run of sorted position 0
+        for (int q = t; q < ns; q += kBinHalf)
+            offs[q] = run[q] - offs[q];
+        __syncthreads();
         for (int j = t; j < nvalid; j += kBinHalf) {
             const int idx = order[j];
             const int sub = stsub[idx];
-            const int pos = run[sub] + (j - offs[sub]);
+            const int pos = offs[sub] + j;
             if (pos < geo.cap) {
+                const uint2 kv = stkv[idx];
                 BinEntry be;
-                be.key = stkey[idx];
-                be.val = stval[idx];
+                be.key = kv.x;
+                be.val = __uint_as_float(kv.y);
                 bins[((int64_t)a * ns + sub) * geo.cap + pos] = be;
             } else {
                 overflow = true;
