@@ -516,8 +516,9 @@ const char *bin_ineligible(const pcdm_problem *P)
 int route_update(pcdm_problem *P)
 {
     // automatic (0) takes the plain gather: on every shape measured so far the
-    // binned route's three launches took longer than the plain gather (the
-    // 1e10-entry instance at tau = 2^20: about 480 us against 427 us)
+    // binned route's three launches were no faster than the plain gather (the
+    // 1e10-entry instance at tau = 2^20: about 441 us against 427-446 us, from
+    // level to 2% slower per step; the 1e6-row instance: 361 us against 145 us)
     const bool ok = bin_ineligible(P) == nullptr;
     const bool want = P->gather_route == 2;
     if (!(ok && want)) {
