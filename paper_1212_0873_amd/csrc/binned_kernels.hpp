@@ -8,7 +8,8 @@
 // step's entries are first regrouped by row, so r is read window by window
 // and every line serves all the entries of the step that fall in it:
 //
-//   k_bin      (one workgroup per 1024 consecutive slots): draws the slots'
+//   k_bin      (one workgroup of 1024 threads per 1024 consecutive slots,
+//              taken in two halves of 512): draws the slots'
 //              coordinates (tau-nice, as the plain gather), keeps x_i and
 //              1/L_i of each slot, and deals the column entries into
 //              sub-bins keyed by (row range, row window), in LDS first and
@@ -45,12 +46,16 @@ constexpr uint32_t kBinWinMask = (1u << kBinWinBits) - 1u;
 constexpr int kBinBlockBits = 14;  // k_bin_dot: 2^14 slots per workgroup
 constexpr int kBinBlock = 1 << kBinBlockBits;
 constexpr int kBinSlotsA = 1024;  // k_bin: slots per workgroup
-constexpr int kBinHalf = 512;     // k_bin: threads, and slots staged at once
+constexpr int kBinHalf = 512;     // k_bin: slots staged at once
+constexpr int kBinThreads = 1024; // k_bin: threads
+constexpr int kBinColsPerWave = kBinHalf / (kBinThreads / 64);  // columns a wave reads per half
+constexpr int kBinRounds = kBinColsPerWave / 8;                 // 8 columns per round
 constexpr int kBinDotThreads = 512;
 constexpr int kBinMaxDpad = 32;   // one 4-entry chunk per lane of an 8-lane group
 constexpr int kBinMaxSub = 1024;  // sub-bins per k_bin workgroup (8 ranges x windows)
 static_assert(kBinWinBits + kBinBlockBits == 32, "key = slot in block | row in window");
 static_assert(kBinBlock % kBinSlotsA == 0, "a k_bin workgroup feeds one k_bin_dot block");
+static_assert(kBinColsPerWave % 8 == 0 && kBinColsPerWave <= 64, "whole rounds of 8 columns, owners in one wave");
 
 struct BinGeom {
     int64_t rx;    // rows per range, ceil(m / 8)
@@ -153,7 +158,7 @@ __device__ __forceinline__ int32_t block_exclusive_scan4(int32_t *v, int cnt, in
 // entries have left) before the first half is sorted and written, so their
 // HBM latency overlaps that work.
 template <typename V>
-__global__ void __launch_bounds__(kBinHalf)
+__global__ void __launch_bounds__(kBinThreads)
 k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restrict__ ctrl, uint64_t seed,
       int64_t tau, uint32_t n, int32_t *__restrict__ id_slot, v2d_t *__restrict__ hdr,
       BinEntry *__restrict__ bins, int32_t *__restrict__ counts, uint32_t *__restrict__ over)
@@ -161,7 +166,7 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     using VT = typename ValT<V>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_keys[kNiceRounds];
-    __shared__ int32_t s_wtot[kBinHalf / 64];
+    __shared__ int32_t s_wtot[kBinThreads / 64];
     const int ns = geo.ns, dpad = geo.dpad;
     const int nstage = kBinHalf * dpad;
     int32_t *cnt = reinterpret_cast<int32_t *>(smem);
@@ -176,7 +181,7 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     const int lane = t & 63, w = t >> 6, gl = lane & 7, grp = lane >> 3;
     const int e = 4 * gl;  // this lane's 4-entry chunk of each column it reads
     const int64_t a = blockIdx.x;
-    for (int q = t; q < ns; q += kBinHalf) {
+    for (int q = t; q < ns; q += kBinThreads) {
         cnt[q] = 0;
         fill[q] = 0;
         run[q] = 0;
@@ -184,21 +189,24 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     const uint64_t k = ctrl->k;
     const NiceKey key = nice_key_block(seed, k, n, s_keys);  // synchronises the block
 
-    // entries of one half: in round q the 8 lanes of group grp read column
-    // q * 8 + grp of this wave, one 4-entry chunk each (dpad <= 32).  The
-    // loads are unconditional (an idle lane reads column 0's first chunk,
-    // always present, and ignores it): loads under a branch would make the
-    // compiler wait for each round's data before issuing the next round.
-    int rw[8][4];
-    VT v[8][4];
-    bool cact[8];
+    // entries of one half: wave w reads the columns of slots
+    // [w * kBinColsPerWave, (w + 1) * kBinColsPerWave) of the half, whose
+    // coordinates lanes 0..kBinColsPerWave-1 draw; in round q the 8 lanes of
+    // group grp read column q * 8 + grp of the wave, one 4-entry chunk each
+    // (dpad <= 32).  The loads are unconditional (an idle lane reads column
+    // 0's first chunk, always present, and ignores it): loads under a branch
+    // would make the compiler wait for each round's data before issuing the
+    // next round.
+    int rw[kBinRounds][4];
+    VT v[kBinRounds][4];
+    bool cact[kBinRounds];
     bool hact = false;
     int64_t hslot = 0;
     uint32_t hid = 0;
     v2d_t hv;
     auto load_half = [&](int h) {
-        hslot = a * kBinSlotsA + (int64_t)h * kBinHalf + t;
-        hact = hslot < tau;
+        hslot = a * kBinSlotsA + (int64_t)h * kBinHalf + w * kBinColsPerWave + lane;
+        hact = lane < kBinColsPerWave && hslot < tau;
         int64_t off = 0;
         hid = 0;
         if (hact) {
@@ -208,7 +216,7 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
         hv = ld_rec(reinterpret_cast<const v2d_t *>(seg + off));
         const int el = e < dpad ? e : 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < kBinRounds; ++q) {
             const int o = q * 8 + grp;
             const int64_t coff = __shfl(off, o);
             cact[q] = __shfl((int)hact, o) != 0 && e < dpad;
@@ -234,8 +242,8 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
         store_half();
         // stage this half's entries in LDS, keyed and counted by sub-bin
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int sl = w * 64 + q * 8 + grp;  // staged column within the half
+        for (int q = 0; q < kBinRounds; ++q) {
+            const int sl = w * kBinColsPerWave + q * 8 + grp;  // staged column within the half
             if (e < dpad) {
                 // slot of column sl within its k_bin_dot block
                 const uint32_t sblk =
@@ -285,17 +293,17 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
         __syncthreads();
         block_exclusive_scan(cnt, offs, ns, s_wtot);  // ends with a barrier
         const int nvalid = offs[ns - 1] + cnt[ns - 1];
-        for (int idx = t; idx < nstage; idx += kBinHalf) {
+        for (int idx = t; idx < nstage; idx += kBinThreads) {
             const uint16_t sub = stsub[idx];
             if (sub != 0xFFFFu)
                 order[offs[sub] + atomicAdd(&fill[sub], 1)] = (uint16_t)idx;
         }
         __syncthreads();
         // offs[q] becomes the place in the sub-bin's run of sorted position 0
-        for (int q = t; q < ns; q += kBinHalf)
+        for (int q = t; q < ns; q += kBinThreads)
             offs[q] = run[q] - offs[q];
         __syncthreads();
-        for (int j = t; j < nvalid; j += kBinHalf) {
+        for (int j = t; j < nvalid; j += kBinThreads) {
             const int idx = order[j];
             const int sub = stsub[idx];
             const int pos = offs[sub] + j;
@@ -310,14 +318,14 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
             }
         }
         __syncthreads();
-        for (int q = t; q < ns; q += kBinHalf) {
+        for (int q = t; q < ns; q += kBinThreads) {
             run[q] += cnt[q];
             cnt[q] = 0;
             fill[q] = 0;
         }
         __syncthreads();
     }
-    for (int q = t; q < ns; q += kBinHalf)
+    for (int q = t; q < ns; q += kBinThreads)
         counts[a * ns + q] = run[q] < geo.cap ? run[q] : geo.cap;
     if (overflow)
         atomicOr(over + (k & 1), 1u);
