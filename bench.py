@@ -38,7 +38,7 @@ WORKLOAD_NAMES = {
     "train_1e5x1e6": "lasso_1e5x1e6_d10_uniform",
     "lasso_2e8x5e8": "lasso_2e8x5e8_d20_balanced",
 }
-KERNEL_SOURCES = ("kernels.hpp", "sampler.hpp", "pcdm.hip")
+KERNEL_SOURCES = ("kernels.hpp", "sampler.hpp", "binned_kernels.hpp", "pcdm.hip")
 
 
 def kernel_source_hash() -> str:
@@ -1075,9 +1075,13 @@ def main() -> int:
     achieved = gather_bytes / gather_avg_s / 1e9
     step_alg_bytes = b_gather * updates + b_scatter * nz
     workload = WORKLOAD_NAMES[args.config]
-    traffic = read_traffic("gather", args.config, args.dtype, tau)
+    # the partial derivatives by rows take three launches per step (their
+    # summed time is the "gather" clock); their counters sit in files of their own
+    by_rows = info["gather_route"] == 2
+    pmc_name = "gather_by_rows" if by_rows else "gather"
+    traffic = read_traffic(pmc_name, args.config, args.dtype, tau)
     ceiling = random_gather_ceiling(A.m)
-    l2c = read_l2_counters("gather", args.config, args.dtype, tau)
+    l2c = read_l2_counters(pmc_name, args.config, args.dtype, tau)
     l2 = {"random_read_ceiling": ceiling, "requests_per_launch": None, "hit_rate": None,
           "request_rate_per_s": None, "frac_of_random_ceiling": None}
     if l2c:
@@ -1107,7 +1111,8 @@ def main() -> int:
                    "gather_route": {1: "columns", 2: "rows"}[info["gather_route"]],
                    "scatter_route": {1: "atomics", 2: "row blocks"}[info["scatter_route"]],
                    "device": dev_name},
-        "roofline": {"bound": "hbm", "kernel": "k_gather", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_bin + k_bin_dot + k_bin_prox" if by_rows else "k_gather",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "alg_bytes_per_update": b_gather,
                      "launches": ng, "avg_launch_us": gather_avg_s * 1e6,

@@ -297,7 +297,9 @@ const char *pcdm_last_error(void);
  *                      8 ceil(tau/1024) * 8 ceil(m/2^21) * cap + 48 tau bytes.
  *                      It reads each line of r about once per step instead
  *                      of once per entry, but its three launches are bound by
- *                      latency; 0 (default) = 1.  pcdm_info.gather_route
+ *                      latency; 0 (default) = 2 where eligible when r (m
+ *                      float32 values) takes at least 256 MiB and tau >= 2^20,
+ *                      else 1.  pcdm_info.gather_route
  *                      reports the route in effect;
  *   "bin_capacity"     route 2: entries per bin (0 = default: the mean count
  *                      for rows spread evenly, plus seven standard deviations

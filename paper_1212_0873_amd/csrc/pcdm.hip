@@ -515,12 +515,15 @@ const char *bin_ineligible(const pcdm_problem *P)
 // (called from API calls only, never inside a captured step).
 int route_update(pcdm_problem *P)
 {
-    // automatic (0) takes the plain gather: on every shape measured so far the
-    // binned route's three launches were no faster than the plain gather (the
-    // 1e10-entry instance at tau = 2^20: about 441 us against 427-446 us, from
-    // level to 2% slower per step; the 1e6-row instance: 361 us against 145 us)
+    // automatic (0) takes the binned route only where it was measured to win:
+    // r larger than the 256 MB Infinity Cache, so that the plain gather's
+    // random reads of r are line fills from HBM, and tau >= 2^20, so that
+    // k_bin_dot has two workgroups per CU (the 1e10-entry instance at
+    // tau = 2^20: 434 against 438 us per step, with 1.7 instead of 3.0 GB past
+    // L2; the 1e6-row instance, r = 4 MB: 361 against 145 us)
     const bool ok = bin_ineligible(P) == nullptr;
-    const bool want = P->gather_route == 2;
+    const bool large = P->m * (int64_t)P->tbytes >= ((int64_t)256 << 20) && P->tau >= ((int64_t)1 << 20);
+    const bool want = P->gather_route == 2 || (P->gather_route == 0 && large);
     if (!(ok && want)) {
         P->binned = false;
         free_bins(P);

@@ -114,7 +114,9 @@ def big(pc, request):
     p.set_option("lambda", 0.05 * inf["atb_inf"])
     _say(f"created ({time.time() - t0:.0f} s): omega {inf['omega']}, beta {inf['beta']:.6f}, "
          f"||A^T b||_inf {inf['atb_inf']:.15e}, gather route {inf['gather_route']}")
-    assert inf["gather_route"] == 1  # plain gather by default
+    # automatic route: by rows here (r = 800 MB, beyond the Infinity Cache, and tau = 2^20);
+    # the plan below sets each step's route explicitly
+    assert inf["gather_route"] == 2
     yield {"p": p, "host": host, "thread": th, "t0": t0, "dtype": dtype}
     p.close()
     torch.cuda.empty_cache()
@@ -166,7 +168,7 @@ def test_full_size_steps_match_oracle(big):
     ref = oracle.ColumnSetSolver(m, n, host["b"], lam, oracle.beta_nice(st.omega, BIG_TAU, n))
     touched = np.zeros(0, dtype=np.int64)
     # (step, tau, gather route)
-    plan = [(0, BIG_TAU, 1), (1, BIG_TAU, 2), (2, BIG_TAU, 1), (3, 1 << 16, 1), (4, 1 << 16, 1), (5, 1 << 16, 1)]
+    plan = [(0, BIG_TAU, 2), (1, BIG_TAU, 1), (2, BIG_TAU, 2), (3, 1 << 16, 1), (4, 1 << 16, 1), (5, 1 << 16, 1)]
     for k, tau, route in plan:
         if tau != p.info()["tau"]:
             p.set_option("tau", tau)
