@@ -180,7 +180,7 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     const int t = threadIdx.x;
     const int lane = t & 63, w = t >> 6, gl = lane & 7, grp = lane >> 3;
     const int e = 4 * gl;  // this lane's 4-entry chunk of each column it reads
-    const int64_t a = blockIdx.x;
+    const int64_t na = (tau + kBinSlotsA - 1) / kBinSlotsA;  // chunks of 1024 slots
     for (int q = t; q < ns; q += kBinThreads) {
         cnt[q] = 0;
         fill[q] = 0;
@@ -204,8 +204,8 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
     int64_t hslot = 0;
     uint32_t hid = 0;
     v2d_t hv;
-    auto load_half = [&](int h) {
-        hslot = a * kBinSlotsA + (int64_t)h * kBinHalf + w * kBinColsPerWave + lane;
+    auto load_half = [&](int64_t ca, int h) {
+        hslot = ca * kBinSlotsA + (int64_t)h * kBinHalf + w * kBinColsPerWave + lane;
         hact = lane < kBinColsPerWave && hslot < tau;
         int64_t off = 0;
         hid = 0;
@@ -234,99 +234,111 @@ k_bin(const char *__restrict__ seg, Layout lay, BinGeom geo, const Ctrl *__restr
 
     bool overflow = false;
     const double inv_rx = 1.0 / (double)geo.rx;
-    load_half(0);
-    // unrolled: the second half's loads land in the registers its staging
-    // reads, with no copies across a loop edge that would wait for them
+    // workgroup blockIdx.x takes chunks blockIdx.x, + gridDim.x, ... (the
+    // grid is one workgroup per CU, which is all the LDS allows); the first
+    // half of its next chunk is loaded while the second half of this one is
+    // sorted and written
+    int64_t a = blockIdx.x;
+    if (a < na)
+        load_half(a, 0);
+    for (; a < na; a += gridDim.x) {
+        // unrolled: the second half's loads land in the registers its staging
+        // reads, with no copies across a loop edge that would wait for them
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        store_half();
-        // stage this half's entries in LDS, keyed and counted by sub-bin
+        for (int h = 0; h < 2; ++h) {
+            store_half();
+            // stage this half's entries in LDS, keyed and counted by sub-bin
 #pragma unroll
-        for (int q = 0; q < kBinRounds; ++q) {
-            const int sl = w * kBinColsPerWave + q * 8 + grp;  // staged column within the half
-            if (e < dpad) {
-                // slot of column sl within its k_bin_dot block
-                const uint32_t sblk =
-                    (uint32_t)(((a * kBinSlotsA + (int64_t)h * kBinHalf + sl)) & (int64_t)(kBinBlock - 1));
-                uint32_t kk[4];
-                float vv[4];
-                uint16_t ss[4];
+            for (int q = 0; q < kBinRounds; ++q) {
+                const int sl = w * kBinColsPerWave + q * 8 + grp;  // staged column within the half
+                if (e < dpad) {
+                    // slot of column sl within its k_bin_dot block
+                    const uint32_t sblk =
+                        (uint32_t)(((a * kBinSlotsA + (int64_t)h * kBinHalf + sl)) & (int64_t)(kBinBlock - 1));
+                    uint32_t kk[4];
+                    float vv[4];
+                    uint16_t ss[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    kk[u] = 0u;
-                    vv[u] = 0.0f;
-                    ss[u] = 0xFFFFu;
-                    if (cact[q] && v[q][u] != VT(0)) {
-                        const uint32_t row = (uint32_t)rw[q][u];
-                        // row range xr = floor(row / rx): the float64 quotient is
-                        // within one of it, and one comparison each way fixes it
-                        uint32_t xr = (uint32_t)((double)row * inv_rx);
-                        int64_t lo = (int64_t)xr * geo.rx;
-                        if (lo > (int64_t)row) {
-                            xr -= 1u;
-                            lo -= geo.rx;
-                        } else if (lo + geo.rx <= (int64_t)row) {
-                            xr += 1u;
-                            lo += geo.rx;
+                    for (int u = 0; u < 4; ++u) {
+                        kk[u] = 0u;
+                        vv[u] = 0.0f;
+                        ss[u] = 0xFFFFu;
+                        if (cact[q] && v[q][u] != VT(0)) {
+                            const uint32_t row = (uint32_t)rw[q][u];
+                            // row range xr = floor(row / rx): the float64 quotient is
+                            // within one of it, and one comparison each way fixes it
+                            uint32_t xr = (uint32_t)((double)row * inv_rx);
+                            int64_t lo = (int64_t)xr * geo.rx;
+                            if (lo > (int64_t)row) {
+                                xr -= 1u;
+                                lo -= geo.rx;
+                            } else if (lo + geo.rx <= (int64_t)row) {
+                                xr += 1u;
+                                lo += geo.rx;
+                            }
+                            const uint32_t within = row - (uint32_t)lo;
+                            const int sub = (int)(xr * (uint32_t)geo.nw + (within >> kBinWinBits));
+                            kk[u] = (sblk << kBinWinBits) | (within & kBinWinMask);
+                            vv[u] = (float)v[q][u];
+                            ss[u] = (uint16_t)sub;
+                            atomicAdd(&cnt[sub], 1);
                         }
-                        const uint32_t within = row - (uint32_t)lo;
-                        const int sub = (int)(xr * (uint32_t)geo.nw + (within >> kBinWinBits));
-                        kk[u] = (sblk << kBinWinBits) | (within & kBinWinMask);
-                        vv[u] = (float)v[q][u];
-                        ss[u] = (uint16_t)sub;
-                        atomicAdd(&cnt[sub], 1);
                     }
+                    // two 16-byte LDS stores of (key, value) pairs and one 8-byte
+                    // store of sub-bins: padded column lengths are multiples of 4,
+                    // so idx is too
+                    const int idx = sl * dpad + e;
+                    *reinterpret_cast<uint4 *>(stkv + idx) =
+                        make_uint4(kk[0], __float_as_uint(vv[0]), kk[1], __float_as_uint(vv[1]));
+                    *reinterpret_cast<uint4 *>(stkv + idx + 2) =
+                        make_uint4(kk[2], __float_as_uint(vv[2]), kk[3], __float_as_uint(vv[3]));
+                    *reinterpret_cast<ushort4 *>(stsub + idx) = make_ushort4(ss[0], ss[1], ss[2], ss[3]);
                 }
-                // two 16-byte LDS stores of (key, value) pairs and one 8-byte
-                // store of sub-bins: padded column lengths are multiples of 4,
-                // so idx is too
-                const int idx = sl * dpad + e;
-                *reinterpret_cast<uint4 *>(stkv + idx) =
-                    make_uint4(kk[0], __float_as_uint(vv[0]), kk[1], __float_as_uint(vv[1]));
-                *reinterpret_cast<uint4 *>(stkv + idx + 2) =
-                    make_uint4(kk[2], __float_as_uint(vv[2]), kk[3], __float_as_uint(vv[3]));
-                *reinterpret_cast<ushort4 *>(stsub + idx) = make_ushort4(ss[0], ss[1], ss[2], ss[3]);
             }
-        }
-        if (h == 0)
-            load_half(1);  // in flight while this half is sorted and written
-        __syncthreads();
-        block_exclusive_scan(cnt, offs, ns, s_wtot);  // ends with a barrier
-        const int nvalid = offs[ns - 1] + cnt[ns - 1];
-        for (int idx = t; idx < nstage; idx += kBinThreads) {
-            const uint16_t sub = stsub[idx];
-            if (sub != 0xFFFFu)
-                order[offs[sub] + atomicAdd(&fill[sub], 1)] = (uint16_t)idx;
-        }
-        __syncthreads();
-        // offs[q] becomes the place in the sub-bin's run of sorted position 0
-        for (int q = t; q < ns; q += kBinThreads)
-            offs[q] = run[q] - offs[q];
-        __syncthreads();
-        for (int j = t; j < nvalid; j += kBinThreads) {
-            const int idx = order[j];
-            const int sub = stsub[idx];
-            const int pos = offs[sub] + j;
-            if (pos < geo.cap) {
-                const uint2 kv = stkv[idx];
-                BinEntry be;
-                be.key = kv.x;
-                be.val = __uint_as_float(kv.y);
-                bins[((int64_t)a * ns + sub) * geo.cap + pos] = be;
-            } else {
-                overflow = true;
+            if (h == 0)
+                load_half(a, 1);  // in flight while this half is sorted and written
+            else if (a + gridDim.x < na)
+                load_half(a + gridDim.x, 0);  // the next chunk's first half, likewise
+            __syncthreads();
+            block_exclusive_scan(cnt, offs, ns, s_wtot);  // ends with a barrier
+            const int nvalid = offs[ns - 1] + cnt[ns - 1];
+            for (int idx = t; idx < nstage; idx += kBinThreads) {
+                const uint16_t sub = stsub[idx];
+                if (sub != 0xFFFFu)
+                    order[offs[sub] + atomicAdd(&fill[sub], 1)] = (uint16_t)idx;
             }
+            __syncthreads();
+            // offs[q] becomes the place in the sub-bin's run of sorted position 0
+            for (int q = t; q < ns; q += kBinThreads)
+                offs[q] = run[q] - offs[q];
+            __syncthreads();
+            for (int j = t; j < nvalid; j += kBinThreads) {
+                const int idx = order[j];
+                const int sub = stsub[idx];
+                const int pos = offs[sub] + j;
+                if (pos < geo.cap) {
+                    const uint2 kv = stkv[idx];
+                    BinEntry be;
+                    be.key = kv.x;
+                    be.val = __uint_as_float(kv.y);
+                    bins[((int64_t)a * ns + sub) * geo.cap + pos] = be;
+                } else {
+                    overflow = true;
+                }
+            }
+            __syncthreads();
+            for (int q = t; q < ns; q += kBinThreads) {
+                run[q] += cnt[q];
+                cnt[q] = 0;
+                fill[q] = 0;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         for (int q = t; q < ns; q += kBinThreads) {
-            run[q] += cnt[q];
-            cnt[q] = 0;
-            fill[q] = 0;
+            counts[a * ns + q] = run[q] < geo.cap ? run[q] : geo.cap;
+            run[q] = 0;  // cnt and fill are already cleared
         }
-        __syncthreads();
     }
-    for (int q = t; q < ns; q += kBinThreads)
-        counts[a * ns + q] = run[q] < geo.cap ? run[q] : geo.cap;
     if (overflow)
         atomicOr(over + (k & 1), 1u);
 }

@@ -698,7 +698,8 @@ template <typename V> struct Ops {
         const int64_t na = ceil_div(P->tau, kBinSlotsA);
         const int64_t nb = ceil_div(P->tau, kBinBlock);
         hipEvent_t t0 = clock_start(P, s);
-        hipLaunchKernelGGL((k_bin<V>), dim3((unsigned)na), dim3(kBinThreads), bin_lds_bytes(geo.ns, geo.dpad), s,
+        hipLaunchKernelGGL((k_bin<V>), dim3((unsigned)std::min<int64_t>(na, std::max(P->cus, 1))), dim3(kBinThreads),
+                           bin_lds_bytes(geo.ns, geo.dpad), s,
                            (const char *)P->seg, P->lay, geo, (const Ctrl *)P->ctrl, P->seed, P->tau, (uint32_t)P->n,
                            P->id_slot, (v2d_t *)P->bhdr, (BinEntry *)P->bins, P->bcounts, P->bover);
         hipLaunchKernelGGL((k_bin_dot<T>), dim3((unsigned)(kBinRanges * nb)), dim3(kBinDotThreads), 0, s,
